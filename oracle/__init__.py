@@ -1,0 +1,146 @@
+"""CPU oracle for the GPP self-energy reduction -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps the plain C code in ``gpp_oracle.c`` (fp64,
+compensated sums) and ``gpp_oracle_ld.c`` (long-double brute force), which
+share nothing with the HIP library.  Inputs are numpy arrays in the layouts
+documented in ``paper_2008_11326_amd.inputs`` (the shared input generator).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+__all__ = ["sigma_fwd", "sigma_fwd_slice", "sigma_ld", "branch",
+           "grad_entries", "slice_loss", "KIND", "load"]
+
+KIND = {"wtilde_array": 0, "I_eps_array": 1, "aqsntemp": 2, "aqsmtemp": 3}
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_cp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def load():
+    """Load liboracle.so, building it first only if nothing is built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    lib = C.CDLL(_build.LIB)
+    i64 = C.c_int64
+    arrs = [_ip, _cp, _cp, _cp, _cp, _dp, _dp]
+    lib.oracle_sigma_fwd_slice.argtypes = arrs + [i64] * 6 + [
+        C.c_int, _cp, _cp, _dp, _dp]
+    lib.oracle_sigma_fwd_slice.restype = C.c_int
+    lib.oracle_ld_sigma_fwd.argtypes = arrs + [_cp, _cp]
+    lib.oracle_ld_sigma_fwd.restype = C.c_int
+    lib.oracle_branch.argtypes = [C.c_double] * 3
+    lib.oracle_branch.restype = C.c_int
+    lib.oracle_grad_entries.argtypes = arrs + [_cp, _cp, C.c_int, _ip, i64,
+                                               C.c_int, _cp]
+    lib.oracle_grad_entries.restype = C.c_int
+    lib.oracle_slice_loss.argtypes = arrs + [
+        _cp, _cp, C.c_int, i64, i64, C.c_double, C.c_double,
+        C.POINTER(C.c_double), C.c_void_p]
+    lib.oracle_slice_loss.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _args(prob):
+    d = prob.dims
+    dims = np.array([d.number_bands, d.nvband, d.ncouls, d.ngpown, d.nfreq],
+                    dtype=np.int64)
+    return [dims, np.ascontiguousarray(prob.aqsmtemp),
+            np.ascontiguousarray(prob.aqsntemp),
+            np.ascontiguousarray(prob.I_eps_array),
+            np.ascontiguousarray(prob.wtilde_array),
+            np.ascontiguousarray(prob.vcoul, dtype=np.float64),
+            np.ascontiguousarray(prob.wx_array, dtype=np.float64)]
+
+
+def sigma_fwd_slice(prob, n=(None, None), p=(None, None), g=(None, None),
+                    nthreads: int = 0):
+    """(achtemp, asxtemp, sum|ch terms|, sum|sx terms|) over a slice of
+    bands/columns/rows; each complex [nfreq] / real [nfreq]."""
+    d = prob.dims
+    n0 = 0 if n[0] is None else n[0]
+    n1 = d.number_bands if n[1] is None else n[1]
+    p0 = 0 if p[0] is None else p[0]
+    p1 = d.ngpown if p[1] is None else p[1]
+    g0 = 0 if g[0] is None else g[0]
+    g1 = d.ncouls if g[1] is None else g[1]
+    nw = d.nfreq
+    ach = np.zeros(nw, np.complex128)
+    asx = np.zeros(nw, np.complex128)
+    ach_abs = np.zeros(nw)
+    asx_abs = np.zeros(nw)
+    rc = load().oracle_sigma_fwd_slice(*_args(prob), n0, n1, p0, p1, g0, g1,
+                                       int(nthreads), ach, asx, ach_abs,
+                                       asx_abs)
+    if rc != 0:
+        raise ValueError("oracle_sigma_fwd_slice: invalid dims or ranges")
+    return ach, asx, ach_abs, asx_abs
+
+
+def sigma_fwd(prob, nthreads: int = 0):
+    """Full reduction: (achtemp, asxtemp, sum|ch|, sum|sx|)."""
+    return sigma_fwd_slice(prob, nthreads=nthreads)
+
+
+def sigma_ld(prob):
+    """Long-double brute force (tiny problems only): (achtemp, asxtemp)."""
+    nw = prob.dims.nfreq
+    ach = np.zeros(nw, np.complex128)
+    asx = np.zeros(nw, np.complex128)
+    if load().oracle_ld_sigma_fwd(*_args(prob), ach, asx) != 0:
+        raise ValueError("oracle_ld_sigma_fwd: invalid dims")
+    return ach, asx
+
+
+def branch(x: float, om: complex) -> int:
+    """0 = A (pole term), 1 = B (near-pole limit), 2 = C (zero)."""
+    return int(load().oracle_branch(float(x), float(om.real), float(om.imag)))
+
+
+def grad_entries(prob, ga, gs, array: str, idx, nthreads: int = 0):
+    """Analytic gradient of L = sum_w Re(conj(ga) ach + conj(gs) asx) at the
+    given (row, col) entries of one array; complex [len(idx)]."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1, 2))
+    out = np.zeros(len(idx), np.complex128)
+    rc = load().oracle_grad_entries(
+        *_args(prob), np.ascontiguousarray(ga, dtype=np.complex128),
+        np.ascontiguousarray(gs, dtype=np.complex128), KIND[array], idx,
+        len(idx), int(nthreads), out)
+    if rc != 0:
+        raise ValueError("oracle_grad_entries: invalid arguments")
+    return out
+
+
+def slice_len(prob, array: str) -> int:
+    d = prob.dims
+    per = {"wtilde_array": d.number_bands, "I_eps_array": d.number_bands,
+           "aqsntemp": d.ngpown, "aqsmtemp": d.ncouls}[array]
+    return per * d.nfreq
+
+
+def slice_loss(prob, ga, gs, array: str, i: int, j: int, z: complex):
+    """L restricted to terms touching entry (i, j) of `array`, with that
+    entry set to z.  Returns (loss, branch codes of the touched terms)."""
+    loss = C.c_double(0.0)
+    br = np.zeros(slice_len(prob, array), dtype=np.int8)
+    rc = load().oracle_slice_loss(
+        *_args(prob), np.ascontiguousarray(ga, dtype=np.complex128),
+        np.ascontiguousarray(gs, dtype=np.complex128), KIND[array], int(i),
+        int(j), float(np.real(z)), float(np.imag(z)), C.byref(loss),
+        br.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_slice_loss: invalid arguments")
+    return loss.value, br

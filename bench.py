@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the GPP forward reduction (achtemp/asxtemp, Sec. II-A) on
+one MI355X.
+
+A step is one gpp_sigma_fwd call (tile kernel + fixed-order reduction
+kernel) over the synthetic workload with the per-task shape of the paper's
+Si-system run: number_bands=512, nvband=2, ncouls=32768, ngpown=1638,
+nfreq=3, inputs resident in HBM.  Prints one JSON line on stdout.
+
+    python bench.py [--steps K] [--warmup W] [--workload si|small|adjoint|large]
+
+Throughput is algorithmic: 21 fp64 operations per Coulomb-hole term plus
+21 per screened-exchange term (the arithmetic the method needs, fixed
+independently of the implementation), divided by the measured time.  The
+roofline block compares it with the MI355X fp64 vector-ALU peak.  The CPU
+baseline times the plain oracle on a bounded slice of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GPP FP64 TFLOP/s and % FP64 peak; batched/adjoint vs plain at 1e-12 rel"
+FLOP_PER_TERM = 21
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 fp64 FLOP/clk/CU
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, target_seconds):
+    """Time the CPU oracle on the first k G' columns (all bands and rows)."""
+    import oracle  # test infrastructure: only this leg of the benchmark uses it
+    d = prob.dims
+    threads = len(os.sched_getaffinity(0))
+    per_col = (d.number_bands + d.nvband) * d.ncouls * d.nfreq
+    k0 = min(threads, d.ngpown)
+    t0 = time.perf_counter()
+    oracle.sigma_fwd_slice(prob, p=(0, k0), nthreads=threads)
+    t_cal = time.perf_counter() - t0
+    rate = k0 * per_col / max(t_cal, 1e-6)
+    k = int(max(k0, min(d.ngpown, target_seconds * rate / per_col)))
+    k = max(threads, (k // threads) * threads) if k > threads else k
+    k = min(k, d.ngpown)
+    t0 = time.perf_counter()
+    oracle.sigma_fwd_slice(prob, p=(0, k), nthreads=threads)
+    dt = time.perf_counter() - t0
+    terms = k * per_col
+    return {
+        "value": FLOP_PER_TERM * terms / dt / 1e12, "unit": "TFLOP/s",
+        "cores": min(threads, k), "kind": "oracle",
+        "sample": f"G' columns p in [0,{k}) of {d.ngpown}, all {d.number_bands} bands "
+                  f"and {d.ncouls} rows, nfreq={d.nfreq}: {terms:.3e} terms in {dt:.1f} s",
+        "terms_per_s": terms / dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="si")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        msg = (f"bench.py measures one GPU only (asked for --gpus {args.gpus}, "
+               f"WORLD_SIZE={world}); multi-GPU G'-column sharding is not built")
+        print(msg, file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2008_11326_amd as gpp
+    from paper_2008_11326_amd import _lib
+    from paper_2008_11326_amd import inputs as I
+
+    _lib.load()  # fail loudly if the HIP library is missing
+    wl = I.WORKLOADS[args.workload]
+    d = wl.dims
+    log(f"[bench] generating {wl.name}")
+    t0 = time.perf_counter()
+    prob = I.make_problem(d, wl.seed, wl.pole_fraction)
+    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    t_in = [to(a) for a in prob.arrays()]
+    ach = torch.empty(d.nfreq, dtype=torch.complex128, device=dev)
+    asx = torch.empty(d.nfreq, dtype=torch.complex128, device=dev)
+    ws = torch.empty(gpp.fwd_workspace_bytes(*d.as_tuple()), dtype=torch.uint8,
+                     device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        gpp.sigma_fwd(*t_in, nvband=d.nvband, out=(ach, asx), workspace=ws,
+                      stream=stream.cuda_stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # events on the stream the kernels are launched on
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_all0.record(stream)
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_all0.elapsed_time(t_all1)
+    per_launch_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = total_ms / args.steps
+    launch_ms = sum(per_launch_ms) / len(per_launch_ms)
+    log(f"[bench] {args.steps} steps: {total_ms:.3f} ms on device, {wall * 1e3:.3f} ms wall; "
+        f"per launch min {min(per_launch_ms):.3f} max {max(per_launch_ms):.3f} ms")
+
+    terms = d.ch_terms + d.sx_terms
+    flops = FLOP_PER_TERM * terms
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "number_bands": d.number_bands,
+                   "nvband": d.nvband, "ncouls": d.ncouls, "ngpown": d.ngpown,
+                   "nfreq": d.nfreq, "seed": wl.seed,
+                   "pole_fraction": wl.pole_fraction},
+        "pct_fp64_peak": round(100.0 * value / FP64_VECTOR_PEAK_TFLOPS, 2),
+        "terms_per_s": terms / (ms_per_step * 1e-3),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4),
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": None,
+                     "kernel": "gpp::fwd_tiles<3> + reduce_partials (one launch pair)",
+                     "launch_ms": round(launch_ms, 4)},
+    }
+    res = (ach.cpu().numpy(), asx.cpu().numpy())
+    from tests.gpu_helpers import load_golden, rel_errors
+    gold = load_golden(args.workload)
+    if gold is not None:
+        e = max(rel_errors(res[0], gold["ach"], gold["ach_abs_sum"]).max(),
+                rel_errors(res[1], gold["asx"], gold["asx_abs_sum"]).max())
+        out["max_rel_err_vs_oracle"] = float(e)
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded slice")
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,119 @@
+/*
+ * gpp.h -- C ABI of the MI355X (gfx950) GPP self-energy library, libgpp.so.
+ *
+ * The operation (paper Sec. II-A, pseudo-code of the GPP kernel, with the
+ * branch skeleton of Sec. III v2 and squared compares of v3):
+ *
+ *   achtemp[w] = sum_{n<NB} sum_{p<NP} sum_{g<NG}  vcoul[g]/2 * M * sch(n,p,g,w)
+ *   asxtemp[w] = sum_{n<NV} sum_{p<NP} sum_{g<NG}  vcoul[g]   * M * ssx(n,p,g,w)
+ *   M = aqsntemp[n][g] * conj(aqsmtemp[n][p]),  x = wx_array[w][n],
+ *   om = wtilde_array[p][g],  e = I_eps_array[p][g]
+ *
+ *   dr = x - Re om, wi2 = (Im om)^2, wdiffr = fma(dr, dr, wi2),
+ *   wtr = fma(Re om, Re om, wi2)                       (all fp64, round-to-nearest)
+ *   branch A: wdiffr > 0.25 and wtr < fl(250000 * wdiffr)
+ *             sch = e om / (x - om),  ssx = e om^2 / ((x - om)(x + om))
+ *   branch B: not A and wtr > fl(1e-12 * wdiffr)
+ *             sch = 0,                ssx = -e om / (2 (x + om))
+ *   branch C: otherwise sch = ssx = 0
+ *
+ * NB = number_bands, NV = nvband (occupied bands), NG = ncouls (G rows),
+ * NP = ngpown (G' columns held by this process), NW = nfreq.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *    tensors) unless marked "host".  Complex arrays are interleaved
+ *    (re, im) fp64 pairs, row-major with the last index fastest; complex
+ *    pointers must be 16-byte aligned, real ones 8-byte aligned.
+ *  - The caller owns every buffer, including the workspace; the library
+ *    keeps no pointer after a call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *    stream) and the call returns without synchronising.  Outputs are
+ *    overwritten, never accumulated into.
+ *  - Arguments are validated before anything is enqueued; a failed check
+ *    returns GPP_ERR_INVALID (or GPP_ERR_WORKSPACE) and touches nothing.
+ *    HIP runtime failures return GPP_ERR_HIP.  gpp_last_error() gives a
+ *    thread-local message for the most recent failure.  No C++ exception
+ *    crosses this interface.
+ *  - Inputs must be finite; non-finite inputs give unspecified outputs.
+ *  - Results are deterministic: the same inputs, sizes and device give
+ *    bitwise-identical outputs (fixed-order reductions, no atomics).
+ */
+#ifndef GPP_H
+#define GPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GPP_OK = 0,
+    GPP_ERR_INVALID = 1,     /* bad dims, NULL or misaligned pointer      */
+    GPP_ERR_HIP = 2,         /* a HIP runtime call failed                 */
+    GPP_ERR_NOMEM = 3,       /* host allocation failed                    */
+    GPP_ERR_WORKSPACE = 4,   /* workspace NULL or smaller than required   */
+    GPP_ERR_UNSUPPORTED = 5  /* device is not gfx950 / no device          */
+} gpp_status;
+
+/* Loop bounds (Sec. II-A).  Requirements: 0 <= nvband <= number_bands,
+ * 0 <= ngpown <= ncouls, 1 <= nfreq <= GPP_MAX_NFREQ, every value below
+ * 2^31.  number_bands, ncouls or ngpown may be 0 (outputs are then 0). */
+typedef struct {
+    int64_t number_bands;
+    int64_t nvband;
+    int64_t ncouls;
+    int64_t ngpown;
+    int64_t nfreq;
+} gpp_dims;
+
+#define GPP_MAX_NFREQ 8
+
+/* Device input arrays (read only).  A pointer may be NULL only when its
+ * array has no elements. */
+typedef struct {
+    const double *aqsmtemp;     /* complex [number_bands][ncouls]; only the
+                                   first ngpown columns are read          */
+    const double *aqsntemp;     /* complex [number_bands][ncouls]          */
+    const double *I_eps_array;  /* complex [ngpown][ncouls]                */
+    const double *wtilde_array; /* complex [ngpown][ncouls]                */
+    const double *vcoul;        /* real    [ncouls]                        */
+    const double *wx_array;     /* real    [nfreq][number_bands]           */
+} gpp_inputs;
+
+/* Bytes of device workspace gpp_sigma_fwd needs for `dims` (host-only
+ * computation, no device call).  Returns 0 for invalid dims. */
+size_t gpp_sigma_fwd_workspace(const gpp_dims *dims);
+
+/*
+ * gpp_sigma_fwd -- the reduction above (Sec. II-A), one G'-column share.
+ *   dims, in:        host pointer
+ *   achtemp, asxtemp: device, complex [nfreq] each, overwritten
+ *   workspace:       device, >= gpp_sigma_fwd_workspace(dims) bytes,
+ *                    256-byte aligned; contents unspecified afterwards
+ *   stream:          hipStream_t or NULL
+ * Two kernels run on `stream`: the tile kernel writes one partial per
+ * workgroup into the workspace, then one workgroup reduces them in a fixed
+ * order.
+ */
+gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
+                         double *achtemp, double *asxtemp, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* Static string for a status code. */
+const char *gpp_status_string(gpp_status status);
+
+/* Thread-local message describing the most recent failure on this thread
+ * ("" if none).  Valid until the next call on the same thread. */
+const char *gpp_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int gpp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPP_H */

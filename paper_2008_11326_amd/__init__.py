@@ -1,0 +1,110 @@
+"""MI355X-native GPP self-energy reduction (paper Sec. II-A) behind a C ABI.
+
+The computation runs in hand-written HIP kernels for gfx950 (libgpp.so,
+include/gpp.h).  This module only marshals torch CUDA tensors (device
+memory and the current stream) into that ABI.
+
+    ach, asx = sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
+                         vcoul, wx_array, nvband)
+
+Layouts (row-major, last index fastest): aqsmtemp/aqsntemp complex128
+[number_bands, ncouls]; I_eps_array/wtilde_array complex128 [ngpown, ncouls];
+vcoul float64 [ncouls]; wx_array float64 [nfreq, number_bands].  Outputs
+are complex128 [nfreq].
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import GppError, MAX_NFREQ
+
+__all__ = ["sigma_fwd", "fwd_workspace_bytes", "GppError", "MAX_NFREQ",
+           "library_path"]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t.numel() > 0 else C.c_void_p(0)
+
+
+def _check_tensor(name, t, dtype, shape, device):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _prepare(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
+             nvband):
+    torch = _torch()
+    if aqsntemp.dim() != 2 or I_eps_array.dim() != 2 or wx_array.dim() != 2:
+        raise ValueError("aqsntemp, I_eps_array and wx_array must be 2-D")
+    nb, ng = aqsntemp.shape
+    npw = I_eps_array.shape[0]
+    nw = wx_array.shape[0]
+    dev = aqsntemp.device
+    if dev.type != "cuda":
+        raise ValueError("inputs must be CUDA (HIP) tensors")
+    c128, f64 = torch.complex128, torch.float64
+    _check_tensor("aqsmtemp", aqsmtemp, c128, (nb, ng), dev)
+    _check_tensor("aqsntemp", aqsntemp, c128, (nb, ng), dev)
+    _check_tensor("I_eps_array", I_eps_array, c128, (npw, ng), dev)
+    _check_tensor("wtilde_array", wtilde_array, c128, (npw, ng), dev)
+    _check_tensor("vcoul", vcoul, f64, (ng,), dev)
+    _check_tensor("wx_array", wx_array, f64, (nw, nb), dev)
+    dims = _lib.dims_struct(nb, nvband, ng, npw, nw)
+    ins = _lib.GppInputs(_ptr(aqsmtemp), _ptr(aqsntemp), _ptr(I_eps_array),
+                         _ptr(wtilde_array), _ptr(vcoul), _ptr(wx_array))
+    return dims, ins, dev
+
+
+def fwd_workspace_bytes(number_bands, nvband, ncouls, ngpown, nfreq) -> int:
+    d = _lib.dims_struct(number_bands, nvband, ncouls, ngpown, nfreq)
+    return int(_lib.load().gpp_sigma_fwd_workspace(C.byref(d)))
+
+
+def sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
+              nvband: int, *, out=None, workspace=None, stream=None):
+    """achtemp, asxtemp (complex128 [nfreq] each) via gpp_sigma_fwd.
+
+    `out` may be a pair of preallocated complex128 [nfreq] tensors and
+    `workspace` a uint8 tensor of at least fwd_workspace_bytes(...) bytes;
+    `stream` defaults to torch's current stream on the inputs' device."""
+    torch = _torch()
+    lib = _lib.load()
+    dims, ins, dev = _prepare(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
+                              vcoul, wx_array, nvband)
+    nw = dims.nfreq
+    if out is None:
+        ach = torch.empty(nw, dtype=torch.complex128, device=dev)
+        asx = torch.empty(nw, dtype=torch.complex128, device=dev)
+    else:
+        ach, asx = out
+        _check_tensor("achtemp", ach, torch.complex128, (nw,), dev)
+        _check_tensor("asxtemp", asx, torch.complex128, (nw,), dev)
+    need = int(lib.gpp_sigma_fwd_workspace(C.byref(dims)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    st = lib.gpp_sigma_fwd(C.byref(dims), C.byref(ins), _ptr(ach), _ptr(asx),
+                           _ptr(workspace), workspace.numel(),
+                           C.c_void_p(stream))
+    _lib.check(st, "gpp_sigma_fwd")
+    return ach, asx

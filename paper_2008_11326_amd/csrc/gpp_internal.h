@@ -1,0 +1,30 @@
+// gpp_internal.h -- host-side declarations shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gpp {
+
+// Validated loop bounds (every value < 2^31).
+struct Dims32 {
+    int nb, nv, ng, np, nw;
+};
+
+struct DevInputs {
+    const double2 *aqsm, *aqsn, *ieps, *wt;
+    const double *vcoul, *wx;
+};
+
+struct FwdGeometry {
+    long ntiles = 0;     // (ceil(ng/64) g-tiles) x (np columns), one per wave
+    long nblocks = 0;    // workgroups of 4 waves
+    size_t partial_bytes = 0;
+};
+
+FwdGeometry fwd_geometry(const Dims32 &d);
+hipError_t launch_fwd(const Dims32 &d, const DevInputs &in, double2 *ach, double2 *asx,
+                      void *workspace, hipStream_t st);
+
+}  // namespace gpp

@@ -1,0 +1,120 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/gpp.h declares, and rejects invalid arguments before any device
+call (these tests never reach a kernel launch)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2008_11326_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpp_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "gpp_sigma_fwd" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTED) == names
+
+
+def test_status_strings(lib):
+    for code, name in _lib.STATUS.items():
+        assert lib.gpp_status_string(code).decode().startswith(name)
+    assert lib.gpp_version() >= 100
+
+
+def _dims(nb=8, nv=2, ng=100, npw=10, nw=3):
+    return _lib.GppDims(nb, nv, ng, npw, nw)
+
+
+# Fake, aligned device addresses: every case below fails validation first.
+FAKE = 0x7F0000000000
+
+
+def _inputs(**override):
+    vals = dict(aqsmtemp=FAKE, aqsntemp=FAKE + 0x100000,
+                I_eps_array=FAKE + 0x200000, wtilde_array=FAKE + 0x300000,
+                vcoul=FAKE + 0x400000, wx_array=FAKE + 0x500000)
+    vals.update(override)
+    return _lib.GppInputs(*[C.c_void_p(vals[k]) for k, _ in _lib.GppInputs._fields_])
+
+
+def _call(lib, dims, ins, ach=FAKE + 0x600000, asx=FAKE + 0x600100, ws=None,
+          ws_bytes=None):
+    need = lib.gpp_sigma_fwd_workspace(C.byref(dims))
+    ws = FAKE + 0x700000 if ws is None else ws
+    ws_bytes = need if ws_bytes is None else ws_bytes
+    return lib.gpp_sigma_fwd(C.byref(dims), C.byref(ins), C.c_void_p(ach),
+                             C.c_void_p(asx), C.c_void_p(ws), ws_bytes, None)
+
+
+@pytest.mark.parametrize("dims,msg", [
+    (_dims(nv=9), "nvband"),
+    (_dims(npw=101), "ngpown"),
+    (_dims(nw=0), "nfreq"),
+    (_dims(nw=9), "nfreq"),
+    (_dims(nb=-1), "negative"),
+    (_dims(ng=1 << 31, npw=1), "2^31"),
+])
+def test_invalid_dims(lib, dims, msg):
+    assert _call(lib, dims, _inputs()) == 1
+    assert msg in lib.gpp_last_error().decode()
+    assert lib.gpp_sigma_fwd_workspace(C.byref(dims)) == 0
+
+
+@pytest.mark.parametrize("field", [f for f, _ in _lib.GppInputs._fields_])
+def test_null_and_misaligned_inputs(lib, field):
+    assert _call(lib, _dims(), _inputs(**{field: 0})) == 1
+    assert field in lib.gpp_last_error().decode()
+    align = 16 if field not in ("vcoul", "wx_array") else 8
+    assert _call(lib, _dims(), _inputs(**{field: FAKE + 0x800000 + align // 2})) == 1
+    assert "aligned" in lib.gpp_last_error().decode()
+
+
+def test_null_pointer_allowed_for_empty_array(lib):
+    # nvband = 0 and ngpown = 0 are valid; with ngpown = 0 the G'-indexed
+    # arrays may be NULL -- but the workspace check below still fails, so
+    # nothing launches
+    d = _dims(npw=0)
+    ins = _inputs(I_eps_array=0, wtilde_array=0)
+    assert _call(lib, d, ins, ws=0) == 4
+
+
+def test_outputs_and_workspace(lib):
+    assert _call(lib, _dims(), _inputs(), ach=0) == 1
+    assert _call(lib, _dims(), _inputs(), asx=FAKE + 8) == 1
+    assert _call(lib, _dims(), _inputs(), ws=0) == 4
+    d = _dims()
+    need = lib.gpp_sigma_fwd_workspace(C.byref(d))
+    assert need > 0
+    assert _call(lib, d, _inputs(), ws_bytes=need - 1) == 4
+    assert "workspace" in lib.gpp_last_error().decode()
+
+
+def test_workspace_size_is_host_only_and_monotone(lib):
+    small = lib.gpp_sigma_fwd_workspace(C.byref(_dims(ng=64, npw=4)))
+    big = lib.gpp_sigma_fwd_workspace(C.byref(_dims(ng=32768, npw=1638)))
+    assert 0 < small <= big
+    assert lib.gpp_sigma_fwd_workspace(None) == 0
+
+
+def test_python_binding_rejects_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib.load()

@@ -1,0 +1,127 @@
+"""GPU parity of gpp_sigma_fwd against the CPU oracle (the reduction of
+Sec. II-A with the branch of Sec. III v2/v3).  Every complex output entry
+must agree within 1e-12 relative; branch decisions are bit-exact by
+construction, so this holds even with planted near-poles."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11326_amd import inputs as I
+from tests.gpu_helpers import GOLDEN, assert_parity, load_golden, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpp():
+    import paper_2008_11326_amd as gpp
+    from paper_2008_11326_amd import _lib
+    _lib.load()
+    return gpp
+
+
+def run(gpp, prob):
+    import torch
+    d = to_device(prob)
+    ach, asx = gpp.sigma_fwd(**d, nvband=prob.dims.nvband)
+    torch.cuda.synchronize()
+    return ach.cpu().numpy(), asx.cpu().numpy()
+
+
+def check(gpp, prob, what, nthreads=0):
+    say(f"[fwd] {what} dims={prob.dims}")
+    ach, asx = run(gpp, prob)
+    ref = oracle.sigma_fwd(prob, nthreads=nthreads)
+    e1 = assert_parity(ach, ref[0], ref[2], what + " achtemp")
+    e2 = assert_parity(asx, ref[1], ref[3], what + " asxtemp")
+    return max(e1, e2)
+
+
+def test_small_workload(gpp):
+    wl = I.WORKLOADS["small"]
+    prob = I.make_problem(wl.dims, wl.seed)
+    err = check(gpp, prob, wl.name)
+    say(f"[fwd] small max rel err {err:.2e}")
+
+
+with open(os.path.join(GOLDEN, "single_terms.json")) as f:
+    SINGLE = json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", SINGLE, ids=[c["name"] for c in SINGLE])
+def test_single_term_edge_cases(gpp, case):
+    c = lambda v: np.array([[complex(v[0], v[1])]], dtype=np.complex128)
+    prob = I.Problem(I.Dims(1, 1, 1, 1, 1), aqsmtemp=c(case["aqsmtemp"]),
+                     aqsntemp=c(case["aqsntemp"]), I_eps_array=c(case["I_eps"]),
+                     wtilde_array=c(case["wtilde"]), vcoul=np.array([case["vcoul"]]),
+                     wx_array=np.array([[case["x"]]]))
+    check(gpp, prob, case["name"], nthreads=1)
+
+
+def _tile_edge_problem(seed, nb, nv, ng, npw, nw, poles=0.0):
+    return I.make_problem(I.Dims(nb, nv, ng, npw, nw), seed, poles)
+
+
+@pytest.mark.parametrize("shape", [
+    (5, 2, 63, 3, 3), (5, 2, 64, 3, 3), (5, 2, 65, 3, 3), (7, 0, 200, 9, 3),
+    (7, 7, 200, 9, 3), (1, 1, 130, 1, 3), (1, 0, 1, 1, 3), (40, 3, 777, 13, 3),
+    (3, 1, 129, 5, 1), (3, 1, 129, 5, 2), (3, 1, 129, 5, 4), (3, 1, 129, 5, 5),
+    (3, 1, 129, 5, 6), (3, 1, 129, 5, 7), (3, 1, 129, 5, 8),
+])
+def test_ragged_and_nfreq(gpp, shape):
+    prob = _tile_edge_problem(sum(shape), *shape)
+    check(gpp, prob, f"ragged {shape}", nthreads=1)
+
+
+def test_planted_poles(gpp):
+    prob = _tile_edge_problem(17, 24, 4, 1000, 20, 3, poles=0.1)
+    check(gpp, prob, "planted poles 10%")
+
+
+def test_slow_threshold_path(gpp):
+    """|om|^2 >= 62500: the branch-A test depends on the 250000 |d|^2 bound,
+    taken through the exact per-pair threshold."""
+    prob = _tile_edge_problem(23, 16, 2, 300, 12, 3)
+    rng = np.random.default_rng(5)
+    prob.wtilde_array = prob.wtilde_array + 499.0
+    # x within a few units of 500 puts |d|^2 around 1..16 while |om|^2 is
+    # about 2.5e5, so both sides of the |om|^2 < 250000 |d|^2 bound occur
+    prob.wx_array = 500.0 + rng.uniform(-4.0, 4.0, prob.wx_array.shape)
+    ref_br = [oracle.branch(x, om) for x in prob.wx_array.ravel()[:20]
+              for om in prob.wtilde_array.ravel()[:50]]
+    assert 0 in ref_br and 1 in ref_br
+    check(gpp, prob, "slow threshold path")
+
+
+def test_empty_dimensions(gpp):
+    for dims in (I.Dims(0, 0, 64, 4, 3), I.Dims(4, 1, 64, 0, 3),
+                 I.Dims(4, 1, 0, 0, 2)):
+        prob = I.make_problem(dims, 1)
+        ach, asx = run(gpp, prob)
+        assert np.all(ach == 0) and np.all(asx == 0)
+
+
+def test_bitwise_deterministic(gpp):
+    prob = _tile_edge_problem(31, 16, 2, 1000, 30, 3)
+    a1, s1 = run(gpp, prob)
+    a2, s2 = run(gpp, prob)
+    assert np.array_equal(a1, a2) and np.array_equal(s1, s2)
+
+
+@pytest.mark.parametrize("key", ["adjoint", "si"])
+def test_full_size_against_golden(gpp, key):
+    """Full-size workloads in the launch configuration the benchmark times,
+    against oracle outputs written by tests/golden/make_golden.py."""
+    rec = load_golden(key)
+    if rec is None:
+        pytest.skip(f"tests/golden/fwd_{key}.json not generated")
+    wl = I.WORKLOADS[key]
+    say(f"[fwd] full size {wl.name}: generating inputs")
+    prob = I.make_problem(wl.dims, wl.seed, wl.pole_fraction)
+    ach, asx = run(gpp, prob)
+    e1 = assert_parity(ach, rec["ach"], rec["ach_abs_sum"], key + " achtemp")
+    e2 = assert_parity(asx, rec["asx"], rec["asx_abs_sum"], key + " asxtemp")
+    say(f"[fwd] {key} max rel err {max(e1, e2):.2e}")

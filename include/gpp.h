@@ -59,8 +59,9 @@ typedef enum {
 } gpp_status;
 
 /* Loop bounds (Sec. II-A).  Requirements: 0 <= nvband <= number_bands,
- * 0 <= ngpown <= ncouls, 1 <= nfreq <= GPP_MAX_NFREQ, every value below
- * 2^31.  number_bands, ncouls or ngpown may be 0 (outputs are then 0). */
+ * 0 <= ngpown <= ncouls <= GPP_MAX_NCOULS, 1 <= nfreq <= GPP_MAX_NFREQ,
+ * number_bands below 2^31.  number_bands, ncouls or ngpown may be 0
+ * (outputs are then 0). */
 typedef struct {
     int64_t number_bands;
     int64_t nvband;
@@ -70,6 +71,7 @@ typedef struct {
 } gpp_dims;
 
 #define GPP_MAX_NFREQ 8
+#define GPP_MAX_NCOULS (1 << 26)
 
 /* Device input arrays (read only).  A pointer may be NULL only when its
  * array has no elements. */
@@ -92,11 +94,14 @@ size_t gpp_sigma_fwd_workspace(const gpp_dims *dims);
  *   dims, in:        host pointer
  *   achtemp, asxtemp: device, complex [nfreq] each, overwritten
  *   workspace:       device, >= gpp_sigma_fwd_workspace(dims) bytes,
- *                    256-byte aligned; contents unspecified afterwards
+ *                    16-byte aligned; contents unspecified afterwards
  *   stream:          hipStream_t or NULL
- * Two kernels run on `stream`: the tile kernel writes one partial per
- * workgroup into the workspace, then one workgroup reduces them in a fixed
- * order.
+ * Three kernels run on `stream`: the tile kernel writes one partial per
+ * workgroup into the workspace, then two fixed-order reduction stages
+ * produce the outputs (the separate reduction kernel of Sec. II-A).
+ * Masked (branch B/C) Coulomb-hole terms contribute below 2^-1000 in
+ * absolute value, so an output whose exact value is 0 comes back with
+ * magnitude below 1e-300.
  */
 gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
                          double *achtemp, double *asxtemp, void *workspace,

@@ -39,7 +39,7 @@ class GppInputs(C.Structure):
                 ("vcoul", C.c_void_p), ("wx_array", C.c_void_p)]
 
 
-# (name, restype, argtypes) of every symbol include/gpp.h declares
+# (name, restype, argtypes) of every function include/*.h declares
 _SIGNATURES = [
     ("gpp_sigma_fwd_workspace", C.c_size_t, [C.POINTER(GppDims)]),
     ("gpp_sigma_fwd", C.c_int,
@@ -48,6 +48,11 @@ _SIGNATURES = [
     ("gpp_status_string", C.c_char_p, [C.c_int]),
     ("gpp_last_error", C.c_char_p, []),
     ("gpp_version", C.c_int, []),
+    # include/gpp_microbench.h
+    ("gpp_mb_fp64_fma", C.c_int,
+     [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
+    ("gpp_mb_copy", C.c_int,
+     [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgpp.so")
-SOURCES = ["gpp_api.hip", "gpp_fwd.hip"]
+SOURCES = ["gpp_api.hip", "gpp_fwd.hip", "gpp_microbench.hip"]
 HEADERS = ["gpp_device.h", "gpp_internal.h"]
 ARCH = "gfx950"
 
@@ -65,7 +65,7 @@ def is_stale() -> bool:
         return True
     t = os.path.getmtime(LIB)
     files = [os.path.join(CSRC, f) for f in SOURCES + HEADERS]
-    files.append(os.path.join(INCLUDE, "gpp.h"))
+    files += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE)]
     return any(os.path.getmtime(f) > t for f in files)
 
 

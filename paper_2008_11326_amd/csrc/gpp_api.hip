@@ -43,8 +43,11 @@ gpp_status check_dims(const gpp_dims *d, gpp::Dims32 *out)
     if (d->ngpown > d->ncouls)
         return fail(GPP_ERR_INVALID, "ngpown=%lld > ncouls=%lld", (long long)d->ngpown,
                     (long long)d->ncouls);
-    if (d->number_bands > kMax32 || d->ncouls > kMax32 || d->ngpown > kMax32)
+    if (d->number_bands > kMax32 || d->ngpown > kMax32)
         return fail(GPP_ERR_INVALID, "dimension >= 2^31");
+    // rows are addressed with 32-bit byte offsets inside the kernels
+    if (d->ncouls > GPP_MAX_NCOULS)
+        return fail(GPP_ERR_INVALID, "ncouls=%lld > %d", (long long)d->ncouls, GPP_MAX_NCOULS);
     // tile count must index a 32-bit grid
     int64_t gtiles = (d->ncouls + 63) / 64;
     if (gtiles * d->ngpown / 4 + 1 > kMax32)
@@ -96,7 +99,7 @@ size_t gpp_sigma_fwd_workspace(const gpp_dims *dims)
 {
     gpp::Dims32 d;
     if (check_dims(dims, &d) != GPP_OK) return 0;
-    size_t b = gpp::fwd_geometry(d).partial_bytes;
+    size_t b = gpp::fwd_geometry(d).workspace_bytes;
     return b ? b : 256;
 }
 

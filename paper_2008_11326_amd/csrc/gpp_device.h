@@ -69,6 +69,43 @@ __device__ __forceinline__ double rcp_nr2(double d) {
     return r;
 }
 
+// Batch inversion: r[k] = 1/d[k] for K values with d[k] >= 1/4, from one
+// reciprocal of their product.  Prefix products c[k] = d[0]...d[k]; then
+// R = 1/c[K-1] and, walking back, r[k] = R c[k-1] and R <- R d[k].  Costs
+// 3(K-1) multiplies plus one rcp_nr2 instead of K of them; each r[k]
+// carries at most 2K roundings.  A lane whose product would overflow
+// (some d above ~2^(1000/K)) takes the one-by-one path instead.
+template <int K>
+__device__ __forceinline__ void batch_reciprocal(const double (&d)[K], double (&r)[K]) {
+    double c[K];
+    c[0] = d[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) c[k] = c[k - 1] * d[k];
+    if (__builtin_expect(c[K - 1] < 0x1p1000, 1)) {
+        double R = rcp_nr2(c[K - 1]);
+#pragma unroll
+        for (int k = K - 1; k > 0; --k) {
+            r[k] = R * c[k - 1];
+            R = R * d[k];
+        }
+        r[0] = R;
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) r[k] = rcp_nr2(d[k]);
+    }
+}
+
+// keep ? v : (a value of magnitude below 2^-1042) with one 32-bit select:
+// only the high word (sign, exponent, top mantissa bits) is cleared, which
+// leaves a denormal made of v's low word.  Added to any accumulator above
+// 2^-990 in magnitude it changes nothing, so sums are the same as with an
+// exact zero unless the whole sum is below ~2^-1000.
+__device__ __forceinline__ double mask_keep(bool keep, double v) {
+    const int lo = __double2loint(v);
+    const int hi = keep ? __double2hiint(v) : 0;
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double next_up(double t) {
     return __longlong_as_double(__double_as_longlong(t) + 1);  // t > 0
 }
@@ -100,6 +137,25 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
+}
+
+// Element at byte offset `off` of a complex row of `len` elements whose
+// base is wave-uniform: a raw buffer load with the row in a scalar buffer
+// descriptor (gfx9 descriptor word 3 = 0x00020000) and the offset in a
+// vector register.  Offsets at or beyond the row length read as zero.
+__device__ __forceinline__ cplx load_row_elem(const double2 *row, int len, uint32_t off) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double2 *>(row), (short)0, len * (int)sizeof(double2), 0x00020000);
+    const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    return {v.x, v.y};
+}
+
+// Wave total of v, returned as a wave-uniform (scalar-register) value.
+__device__ __forceinline__ double wave_sum_uniform(double v) {
+    const double t = wave_sum(v);
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(t));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(t));
+    return __hiloint2double(hi, lo);
 }
 
 // Map a hardware workgroup id to a logical one so that each of the 8 XCDs

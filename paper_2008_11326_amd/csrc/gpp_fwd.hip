@@ -5,8 +5,8 @@
 // band-inner loop order of Sec. III v4 (bands serial per thread keeps the
 // g-fastest arrays coalesced and reads wtilde/I_eps once).  Within a wave
 // p and n are uniform, so aqsmtemp[n][p] and wx_array[w][n] are scalar
-// loads; the frequencies are register-blocked (all NW in one pass, no
-// redundant recompute as in v5).
+// loads; the frequencies are register-blocked (all NW in one pass, none of
+// v5's recompute).
 //
 // Per lane, e = I_eps[p][g] and vcoul[g] are constant over the band loop,
 // so they multiply once at the end.  For a branch-A term,
@@ -14,15 +14,18 @@
 // so with Qm = aqsntemp[n][g] conj(aqsmtemp[n][p]) the lane accumulates
 //   P1[w] += (r x) Qm,  P2[w] += r Qm
 // and ends with  achtemp += vcoul/2 * e * (om P1 - wtr P2).  The branch-A
-// test is a single compare against a per-(p,g) threshold that reproduces
-// the specification exactly (gpp_device.h); r = 1/wdiffr is a hardware
-// reciprocal plus two Newton steps (the v1 idea: no IEEE divide), and
+// test is one compare against a per-(p,g) threshold that reproduces the
+// specification exactly (gpp_device.h).  r = 1/wdiffr needs no IEEE divide
+// (the v1 idea); the BU*NW reciprocals of a group of BU bands come from a
+// single hardware reciprocal by batch inversion, with wdiffr clamped to
+// >= 1/4 (exact for every branch-A term) so the product is safe, and
 // masked terms select r = 0.  Occupied bands (n < nvband) also evaluate the
 // screened-exchange term with full complex arithmetic.
 //
-// Each workgroup (4 waves) writes one partial per output; a second kernel
-// sums the partials in a fixed order (the separate reduction kernel of
-// Sec. II-A), so results are bitwise reproducible.
+// Each workgroup (4 waves) writes one partial per output into the
+// workspace; two reduction kernels then sum the partials in a fixed order
+// (the separate reduction kernel of Sec. II-A), so results are bitwise
+// reproducible.
 #include "gpp_device.h"
 #include "gpp_internal.h"
 
@@ -30,14 +33,72 @@ namespace gpp {
 
 constexpr int kFwdWaves = 4;
 constexpr int kFwdThreads = kFwdWaves * kWave;
+// Bands per batch-inverted group (K = bands * nfreq reciprocals from one
+// hardware reciprocal) and an optional cap on VGPRs through a minimum
+// number of waves per SIMD; chosen by measurement on MI355X.
+#ifndef GPP_FWD_BANDS
+#define GPP_FWD_BANDS 3
+#endif
+#ifndef GPP_FWD_MIN_WAVES
+#define GPP_FWD_MIN_WAVES 1
+#endif
+constexpr int kFwdBands = GPP_FWD_BANDS;
+constexpr int kRedThreads = 256;
+constexpr long kRedBlocks = 512;  // first reduction stage
 
-template <int NW>
+// CH-only accumulation for BU consecutive unoccupied bands starting at n.
+// aqsntemp[n][g] is read through a buffer descriptor for the row (scalar
+// registers) plus the lane's 32-bit byte offset, so the per-band address
+// arithmetic stays on the scalar unit.
+template <int NW, int BU>
+__device__ __forceinline__ void ch_group(int n, int nb, int ng, const double2 *aqsn,
+                                         uint32_t goff, const double2 *am_col,
+                                         const double *wx, double a, double wi2, double thr,
+                                         cplx (&P1)[NW], cplx (&P2)[NW])
+{
+    constexpr int K = BU * NW;
+    cplx qm[BU];
+    double xs[K], dc[K], r[K];
+    bool isA[K];
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+        const cplx an = load_row_elem(aqsn + (size_t)(n + u) * ng, ng, goff);
+        const cplx am = cload(am_col + (size_t)(n + u) * ng);
+        qm[u] = cmul_conj(an, am);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double dr = xs[k] - a;
+        const double wd = fma(dr, dr, wi2);
+        isA[k] = wd > thr;
+        dc[k] = fmax(wd, kLimitTwo);
+    }
+    batch_reciprocal<K>(dc, r);
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int k = u * NW + w;
+            const double re = mask_keep(isA[k], r[k]);
+            const double rx = re * xs[k];
+            P1[w].re = fma(rx, qm[u].re, P1[w].re);
+            P1[w].im = fma(rx, qm[u].im, P1[w].im);
+            P2[w].re = fma(re, qm[u].re, P2[w].re);
+            P2[w].im = fma(re, qm[u].im, P2[w].im);
+        }
+    }
+}
+
+template <int NW, int BU>
 __global__ void __launch_bounds__(kFwdThreads)
+__attribute__((amdgpu_waves_per_eu(GPP_FWD_MIN_WAVES)))
 fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
           const double2 *__restrict__ aqsm, const double2 *__restrict__ aqsn,
           const double2 *__restrict__ ieps, const double2 *__restrict__ wt,
           const double *__restrict__ vcoul, const double *__restrict__ wx,
-          double2 *__restrict__ partials)
+          double *__restrict__ partials)
 {
     __shared__ double red[kFwdWaves][4 * NW];
     const int lane = threadIdx.x & (kWave - 1);
@@ -68,8 +129,12 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
 
         const double2 *an_col = aqsn + gc;
         const double2 *am_col = aqsm + p;
+        const uint32_t goff = (uint32_t)gc * (uint32_t)sizeof(double2);
+        const cplx e = cload(ieps + (size_t)p * ng + gc);
+        const double v = valid ? vcoul[gc] : 0.0;
+        const cplx ev = cscale(v, e);
 
-        // occupied bands: exchange (SX) and Coulomb-hole (CH) terms
+        // occupied bands: screened exchange (SX) and Coulomb hole (CH)
         for (int n = 0; n < nv; ++n) {
             const cplx an = cload(an_col + (size_t)n * ng);
             const cplx am = cload(am_col + (size_t)n * ng);
@@ -87,8 +152,8 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
                 P2[w].re = fma(r, qm.re, P2[w].re);
                 P2[w].im = fma(r, qm.im, P2[w].im);
                 // ssx / e
-                const cplx d = cmake(dr, -b);     // x - om
-                const cplx s = cmake(x + a, b);   // x + om
+                const cplx d = cmake(dr, -b);    // x - om
+                const cplx s = cmake(x + a, b);  // x + om
                 cplx t = cmake(0.0, 0.0);
                 if (isA) {
                     t = cdiv(cmul(om, om), cmul(d, s));
@@ -98,30 +163,23 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
                 cmac(SX[w], qm, t);
             }
         }
-        // unoccupied bands: CH only -- the hot loop
-#pragma unroll 2
-        for (int n = nv; n < nb; ++n) {
-            const cplx an = cload(an_col + (size_t)n * ng);
-            const cplx am = cload(am_col + (size_t)n * ng);
-            const cplx qm = cmul_conj(an, am);
+        // The exchange sums are finished here and reduced over the wave into
+        // scalar registers, so they hold no vector registers in the hot loop.
+        if (nv > 0) {
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                const double x = wx[(size_t)w * nb + n];
-                const double dr = x - a;
-                const double wd = fma(dr, dr, wi2);
-                const double rr = rcp_nr2(wd);
-                const double r = wd > thr ? rr : 0.0;
-                const double rx = r * x;
-                P1[w].re = fma(rx, qm.re, P1[w].re);
-                P1[w].im = fma(rx, qm.im, P1[w].im);
-                P2[w].re = fma(r, qm.re, P2[w].re);
-                P2[w].im = fma(r, qm.im, P2[w].im);
+                const cplx t = cmul(ev, SX[w]);
+                asx[w] = cmake(wave_sum_uniform(t.re), wave_sum_uniform(t.im));
             }
         }
 
-        const cplx e = cload(ieps + (size_t)p * ng + gc);
-        const double v = valid ? vcoul[gc] : 0.0;
-        const cplx ev = cscale(v, e);
+        // unoccupied bands: CH only -- the hot loop
+        int n = nv;
+        for (; n + BU <= nb; n += BU)
+            ch_group<NW, BU>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, P1, P2);
+        for (; n < nb; ++n)
+            ch_group<NW, 1>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, P1, P2);
+
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             // S = om P1 - wtr P2
@@ -129,15 +187,16 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
             S.re = fma(-wtr, P2[w].re, S.re);
             S.im = fma(-wtr, P2[w].im, S.im);
             ach[w] = cscale(0.5, cmul(ev, S));
-            asx[w] = cmul(ev, SX[w]);
         }
     }
 
-    // wave then workgroup reduction in a fixed order
+    // wave then workgroup reduction in a fixed order; partial row layout
+    // [4 w + 0..3] = achtemp[w].re, .im, asxtemp[w].re, .im
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        double v0 = wave_sum(ach[w].re), v1 = wave_sum(ach[w].im);
-        double v2 = wave_sum(asx[w].re), v3 = wave_sum(asx[w].im);
+        // asx[] already holds wave totals (or zeros)
+        const double v0 = wave_sum(ach[w].re), v1 = wave_sum(ach[w].im);
+        const double v2 = asx[w].re, v3 = asx[w].im;
         if (lane == 0) {
             red[wid][4 * w + 0] = v0;
             red[wid][4 * w + 1] = v1;
@@ -150,44 +209,49 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < kFwdWaves; ++k) s += red[k][threadIdx.x];
-        // partial layout: [block][2 * NW] complex; slot w = achtemp[w],
-        // slot NW + w = asxtemp[w]
-        const int w = threadIdx.x / 4, c = threadIdx.x % 4;
-        const int slot = (c < 2) ? w : NW + w;
-        double *dst = reinterpret_cast<double *>(partials + (size_t)blockIdx.x * 2 * NW + slot);
-        dst[c & 1] = s;
+        partials[(size_t)blockIdx.x * 4 * NW + threadIdx.x] = s;
     }
 }
 
-// Sum `nparts` partials of 2*nw complex slots in a fixed order: thread t
-// takes parts t, t+256, ... in increasing order, then a fixed tree.
-__global__ void __launch_bounds__(256)
-reduce_partials(const double2 *__restrict__ partials, long nparts, int nslots,
-                double2 *__restrict__ out_a, double2 *__restrict__ out_b, int nw)
+// Sum rows of W doubles: block b takes rows [b*chunk, (b+1)*chunk), thread
+// t rows t, t+256, ... of it (coalesced: neighbouring threads read
+// neighbouring rows), then a fixed wave/workgroup tree.  With final set,
+// writes the result as achtemp/asxtemp instead of a row.
+template <int NW>
+__global__ void __launch_bounds__(kRedThreads)
+reduce_rows(const double *__restrict__ in, long nrows, long chunk, double *__restrict__ out,
+            double2 *__restrict__ ach, double2 *__restrict__ asx, int final_stage)
 {
-    __shared__ double sre[256], sim[256];
-    for (int k = 0; k < nslots; ++k) {
-        double re = 0.0, im = 0.0;
-        for (long i = threadIdx.x; i < nparts; i += 256) {
-            double2 v = partials[(size_t)i * nslots + k];
-            re += v.x;
-            im += v.y;
+    constexpr int W = 4 * NW;
+    __shared__ double red[kRedThreads / kWave][W];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const long lo = (long)blockIdx.x * chunk;
+    const long hi = lo + chunk < nrows ? lo + chunk : nrows;
+    double acc[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) acc[j] = 0.0;
+    for (long i = lo + threadIdx.x; i < hi; i += kRedThreads) {
+        const double *row = in + (size_t)i * W;
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[j] += row[j];
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == 0) red[wid][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < W) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRedThreads / kWave; ++k) s += red[k][threadIdx.x];
+        if (!final_stage) {
+            out[(size_t)blockIdx.x * W + threadIdx.x] = s;
+        } else {
+            const int w = threadIdx.x / 4, c = threadIdx.x % 4;
+            double *dst = reinterpret_cast<double *>(c < 2 ? ach + w : asx + w);
+            dst[c & 1] = s;
         }
-        sre[threadIdx.x] = re;
-        sim[threadIdx.x] = im;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (threadIdx.x < h) {
-                sre[threadIdx.x] += sre[threadIdx.x + h];
-                sim[threadIdx.x] += sim[threadIdx.x + h];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            double2 r = make_double2(sre[0], sim[0]);
-            if (k < nw) out_a[k] = r; else out_b[k - nw] = r;
-        }
-        __syncthreads();
     }
 }
 
@@ -207,17 +271,33 @@ FwdGeometry fwd_geometry(const Dims32 &d)
     const long gtiles = (d.ng + kWave - 1) / kWave;
     geo.ntiles = gtiles * d.np;
     geo.nblocks = (geo.ntiles + kFwdWaves - 1) / kFwdWaves;
-    geo.partial_bytes = (size_t)geo.nblocks * 2 * d.nw * sizeof(double2);
+    geo.red_blocks = geo.nblocks < kRedBlocks ? geo.nblocks : kRedBlocks;
+    geo.red_chunk = (geo.nblocks + geo.red_blocks - 1) / geo.red_blocks;
+    const size_t row = 4 * sizeof(double) * d.nw;
+    geo.partial_bytes = (size_t)geo.nblocks * row;
+    geo.stage_bytes = (size_t)geo.red_blocks * row;
+    geo.workspace_bytes = geo.partial_bytes + geo.stage_bytes;
     return geo;
 }
 
 template <int NW>
-static void launch_fwd_nw(const Dims32 &d, const FwdGeometry &geo, const DevInputs &in,
-                          double2 *partials, hipStream_t st)
+static hipError_t launch_fwd_nw(const Dims32 &d, const FwdGeometry &geo, const DevInputs &in,
+                                double2 *ach, double2 *asx, double *ws, hipStream_t st)
 {
-    hipLaunchKernelGGL(fwd_tiles<NW>, dim3((unsigned)geo.nblocks), dim3(kFwdThreads), 0, st,
-                       d.nb, d.nv, d.ng, d.np, geo.ntiles, in.aqsm, in.aqsn, in.ieps,
-                       in.wt, in.vcoul, in.wx, partials);
+    double *partials = ws;
+    double *stage = ws + (size_t)geo.nblocks * 4 * NW;
+    constexpr int BU = NW <= 3 ? kFwdBands : (NW <= 4 ? 2 : 1);
+    hipLaunchKernelGGL((fwd_tiles<NW, BU>), dim3((unsigned)geo.nblocks),
+                       dim3(kFwdThreads), 0, st, d.nb, d.nv, d.ng, d.np, geo.ntiles, in.aqsm,
+                       in.aqsn, in.ieps, in.wt, in.vcoul, in.wx, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_rows<NW>, dim3((unsigned)geo.red_blocks), dim3(kRedThreads), 0,
+                       st, partials, geo.nblocks, geo.red_chunk, stage, ach, asx, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_rows<NW>, dim3(1), dim3(kRedThreads), 0, st, stage,
+                       geo.red_blocks, geo.red_blocks, nullptr, ach, asx, 1);
+    return hipGetLastError();
 }
 
 hipError_t launch_fwd(const Dims32 &d, const DevInputs &in, double2 *ach, double2 *asx,
@@ -228,23 +308,18 @@ hipError_t launch_fwd(const Dims32 &d, const DevInputs &in, double2 *ach, double
         hipLaunchKernelGGL(fill_zero, dim3(1), dim3(64), 0, st, ach, asx, d.nw);
         return hipGetLastError();
     }
-    double2 *partials = static_cast<double2 *>(workspace);
+    double *ws = static_cast<double *>(workspace);
     switch (d.nw) {
-    case 1: launch_fwd_nw<1>(d, geo, in, partials, st); break;
-    case 2: launch_fwd_nw<2>(d, geo, in, partials, st); break;
-    case 3: launch_fwd_nw<3>(d, geo, in, partials, st); break;
-    case 4: launch_fwd_nw<4>(d, geo, in, partials, st); break;
-    case 5: launch_fwd_nw<5>(d, geo, in, partials, st); break;
-    case 6: launch_fwd_nw<6>(d, geo, in, partials, st); break;
-    case 7: launch_fwd_nw<7>(d, geo, in, partials, st); break;
-    case 8: launch_fwd_nw<8>(d, geo, in, partials, st); break;
+    case 1: return launch_fwd_nw<1>(d, geo, in, ach, asx, ws, st);
+    case 2: return launch_fwd_nw<2>(d, geo, in, ach, asx, ws, st);
+    case 3: return launch_fwd_nw<3>(d, geo, in, ach, asx, ws, st);
+    case 4: return launch_fwd_nw<4>(d, geo, in, ach, asx, ws, st);
+    case 5: return launch_fwd_nw<5>(d, geo, in, ach, asx, ws, st);
+    case 6: return launch_fwd_nw<6>(d, geo, in, ach, asx, ws, st);
+    case 7: return launch_fwd_nw<7>(d, geo, in, ach, asx, ws, st);
+    case 8: return launch_fwd_nw<8>(d, geo, in, ach, asx, ws, st);
     default: return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, partials, geo.nblocks,
-                       2 * d.nw, ach, asx, d.nw);
-    return hipGetLastError();
 }
 
 }  // namespace gpp

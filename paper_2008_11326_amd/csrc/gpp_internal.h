@@ -18,9 +18,11 @@ struct DevInputs {
 };
 
 struct FwdGeometry {
-    long ntiles = 0;     // (ceil(ng/64) g-tiles) x (np columns), one per wave
-    long nblocks = 0;    // workgroups of 4 waves
-    size_t partial_bytes = 0;
+    long ntiles = 0;      // (ceil(ng/64) g-tiles) x (np columns), one per wave
+    long nblocks = 0;     // tile-kernel workgroups of 4 waves (one partial each)
+    long red_blocks = 0;  // first reduction stage workgroups
+    long red_chunk = 0;   // partial rows per first-stage workgroup
+    size_t partial_bytes = 0, stage_bytes = 0, workspace_bytes = 0;
 };
 
 FwdGeometry fwd_geometry(const Dims32 &d);

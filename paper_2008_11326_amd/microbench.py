@@ -1,0 +1,78 @@
+"""Empirical ceilings on this GPU: fp64 FMA rate and streaming-copy
+bandwidth (include/gpp_microbench.h).  Prints one JSON line.
+
+    python -m paper_2008_11326_amd.microbench [--copy-mib 2048]
+
+The copy moves exactly 2 * bytes (read + write); under rocprofv3 --pmc its
+FETCH_SIZE / WRITE_SIZE give the factor between counted and real bytes.
+"""
+import argparse
+import ctypes as C
+import json
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--copy-mib", type=int, default=2048)
+    ap.add_argument("--fma-iters", type=int, default=4096)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+
+    import torch
+
+    from . import _lib
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream(dev)
+    props = torch.cuda.get_device_properties(dev)
+    cus = props.multi_processor_count
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(args.reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    res = {"device": props.name, "compute_units": cus}
+    fma = {}
+    for waves_per_simd in (2, 4, 8):
+        blocks = cus * waves_per_simd  # 4 waves per workgroup
+        out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+        flops = C.c_double(0.0)
+
+        def run():
+            _lib.check(lib.gpp_mb_fp64_fma(C.c_void_p(out.data_ptr()), blocks,
+                                           args.fma_iters, C.c_void_p(st.cuda_stream),
+                                           C.byref(flops)), "gpp_mb_fp64_fma")
+        ms = timed(run)
+        fma[str(waves_per_simd)] = round(flops.value / (ms * 1e-3) / 1e12, 3)
+    res["fp64_fma_tflops_by_waves_per_simd"] = fma
+    res["fp64_fma_tflops"] = max(fma.values())
+
+    nbytes = args.copy_mib << 20
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    src.fill_(1)
+
+    def copy():
+        _lib.check(lib.gpp_mb_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                   nbytes, cus * 8, C.c_void_p(st.cuda_stream)),
+                   "gpp_mb_copy")
+    ms = timed(copy)
+    res["copy_bytes_each_way"] = nbytes
+    res["copy_ms"] = round(ms, 4)
+    res["copy_gbps_read_plus_write"] = round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -10,13 +10,17 @@ import pytest
 from paper_2008_11326_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gpp.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gpp_\w+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if h.endswith(".h"):
+            text = open(os.path.join(INCLUDE, h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(gpp_\w+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -69,7 +73,9 @@ def _call(lib, dims, ins, ach=FAKE + 0x600000, asx=FAKE + 0x600100, ws=None,
     (_dims(nw=0), "nfreq"),
     (_dims(nw=9), "nfreq"),
     (_dims(nb=-1), "negative"),
-    (_dims(ng=1 << 31, npw=1), "2^31"),
+    (_dims(ng=1 << 31, npw=1), "ncouls"),
+    (_dims(ng=(1 << 26) + 1, npw=1), "ncouls"),
+    (_dims(nb=1 << 31), "2^31"),
 ])
 def test_invalid_dims(lib, dims, msg):
     assert _call(lib, dims, _inputs()) == 1

@@ -107,6 +107,36 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
                          double *achtemp, double *asxtemp, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* Bytes of device workspace gpp_sigma_bwd needs for `dims` (host-only
+ * computation).  It grows as ceil(ncouls/256) * number_bands * ngpown * 16
+ * bytes (partial sums of the aqsmtemp gradient).  Returns 0 for invalid
+ * dims. */
+size_t gpp_sigma_bwd_workspace(const gpp_dims *dims);
+
+/*
+ * gpp_sigma_bwd -- adjoint of gpp_sigma_fwd for the loss
+ *     L = sum_w Re(conj(grad_achtemp[w]) achtemp[w] + conj(grad_asxtemp[w]) asxtemp[w]),
+ * i.e. the vector-Jacobian product of the reduction of Sec. II-A.  Each
+ * gradient of a complex input z is dL/dRe z + i dL/dIm z (PyTorch's
+ * convention); the branch of Sec. III v2 is piecewise constant and is not
+ * differentiated.  vcoul and wx_array get no gradient.
+ *   grad_achtemp, grad_asxtemp: device, complex [nfreq]
+ *   grad_aqsmtemp:     device, complex [number_bands][ncouls] (columns
+ *                      >= ngpown are set to 0), or NULL to skip
+ *   grad_aqsntemp:     device, complex [number_bands][ncouls] or NULL
+ *   grad_I_eps_array:  device, complex [ngpown][ncouls] or NULL
+ *   grad_wtilde_array: device, complex [ngpown][ncouls] or NULL
+ *   workspace:         device, >= gpp_sigma_bwd_workspace(dims) bytes,
+ *                      256-byte aligned
+ * Every term's wdiff, reciprocal and branch are recomputed (nothing is
+ * kept from the forward).  Outputs are overwritten; deterministic.
+ */
+gpp_status gpp_sigma_bwd(const gpp_dims *dims, const gpp_inputs *in,
+                         const double *grad_achtemp, const double *grad_asxtemp,
+                         double *grad_aqsmtemp, double *grad_aqsntemp,
+                         double *grad_I_eps_array, double *grad_wtilde_array,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
 /* Static string for a status code. */
 const char *gpp_status_string(gpp_status status);
 

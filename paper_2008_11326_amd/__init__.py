@@ -6,6 +6,8 @@ memory and the current stream) into that ABI.
 
     ach, asx = sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
                          vcoul, wx_array, nvband)
+    grads = sigma_bwd(..., grad_achtemp, grad_asxtemp)   # adjoint
+    ach, asx = sigma(...)            # differentiable (GppSigma autograd.Function)
 
 Layouts (row-major, last index fastest): aqsmtemp/aqsntemp complex128
 [number_bands, ncouls]; I_eps_array/wtilde_array complex128 [ngpown, ncouls];
@@ -19,8 +21,8 @@ import ctypes as C
 from . import _lib
 from ._lib import GppError, MAX_NFREQ
 
-__all__ = ["sigma_fwd", "fwd_workspace_bytes", "GppError", "MAX_NFREQ",
-           "library_path"]
+__all__ = ["sigma_fwd", "sigma_bwd", "sigma", "GppSigma", "fwd_workspace_bytes",
+           "bwd_workspace_bytes", "GppError", "MAX_NFREQ", "library_path"]
 
 
 def library_path() -> str:
@@ -108,3 +110,95 @@ def sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
                            C.c_void_p(stream))
     _lib.check(st, "gpp_sigma_fwd")
     return ach, asx
+
+
+def bwd_workspace_bytes(number_bands, nvband, ncouls, ngpown, nfreq) -> int:
+    d = _lib.dims_struct(number_bands, nvband, ncouls, ngpown, nfreq)
+    return int(_lib.load().gpp_sigma_bwd_workspace(C.byref(d)))
+
+
+def sigma_bwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
+              nvband: int, grad_achtemp, grad_asxtemp, *,
+              want=(True, True, True, True), workspace=None, stream=None):
+    """Vector-Jacobian product of sigma_fwd via gpp_sigma_bwd.
+
+    Returns (grad_aqsmtemp, grad_aqsntemp, grad_I_eps_array,
+    grad_wtilde_array), each a complex128 tensor shaped like its input or
+    None where `want` is False.  Gradients follow PyTorch's convention
+    dL/dRe z + i dL/dIm z for L = sum Re(conj(g) * output)."""
+    torch = _torch()
+    lib = _lib.load()
+    dims, ins, dev = _prepare(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
+                              vcoul, wx_array, nvband)
+    nw = dims.nfreq
+    _check_tensor("grad_achtemp", grad_achtemp, torch.complex128, (nw,), dev)
+    _check_tensor("grad_asxtemp", grad_asxtemp, torch.complex128, (nw,), dev)
+    shapes = (aqsmtemp.shape, aqsntemp.shape, I_eps_array.shape, wtilde_array.shape)
+    outs = [torch.empty(sh, dtype=torch.complex128, device=dev) if w else None
+            for sh, w in zip(shapes, want)]
+    need = int(lib.gpp_sigma_bwd_workspace(C.byref(dims)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    p = lambda t: _ptr(t) if t is not None else C.c_void_p(0)
+    st = lib.gpp_sigma_bwd(C.byref(dims), C.byref(ins), _ptr(grad_achtemp),
+                           _ptr(grad_asxtemp), p(outs[0]), p(outs[1]), p(outs[2]),
+                           p(outs[3]), _ptr(workspace), workspace.numel(),
+                           C.c_void_p(stream))
+    _lib.check(st, "gpp_sigma_bwd")
+    return tuple(outs)
+
+
+def _make_function():
+    torch = _torch()
+
+    class GppSigma(torch.autograd.Function):
+        """(achtemp, asxtemp) = GPP reduction; backward runs the hand-written
+        adjoint kernels (gpp_sigma_bwd).  vcoul, wx_array and nvband get no
+        gradient."""
+
+        @staticmethod
+        def forward(ctx, aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul,
+                    wx_array, nvband):
+            ach, asx = sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
+                                 vcoul, wx_array, nvband)
+            ctx.save_for_backward(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
+                                  vcoul, wx_array)
+            ctx.nvband = int(nvband)
+            return ach, asx
+
+        @staticmethod
+        def backward(ctx, g_ach, g_asx):
+            ins = ctx.saved_tensors
+            nw = ins[5].shape[0]
+            dev = ins[0].device
+            zero = lambda: torch.zeros(nw, dtype=torch.complex128, device=dev)
+            g_ach = zero() if g_ach is None else g_ach.contiguous()
+            g_asx = zero() if g_asx is None else g_asx.contiguous()
+            want = tuple(bool(x) for x in ctx.needs_input_grad[:4])
+            if not any(want):
+                return (None,) * 7
+            grads = sigma_bwd(*ins, ctx.nvband, g_ach, g_asx, want=want)
+            return grads + (None, None, None)
+
+    return GppSigma
+
+
+_fn = None
+
+
+def __getattr__(name):
+    # GppSigma is built on first use so importing the package needs no torch
+    global _fn
+    if name == "GppSigma":
+        if _fn is None:
+            _fn = _make_function()
+        return _fn
+    raise AttributeError(name)
+
+
+def sigma(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array, nvband):
+    """Differentiable (achtemp, asxtemp) through GppSigma."""
+    return __getattr__("GppSigma").apply(aqsmtemp, aqsntemp, I_eps_array,
+                                         wtilde_array, vcoul, wx_array, nvband)

@@ -45,6 +45,11 @@ _SIGNATURES = [
     ("gpp_sigma_fwd", C.c_int,
      [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p,
       C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("gpp_sigma_bwd_workspace", C.c_size_t, [C.POINTER(GppDims)]),
+    ("gpp_sigma_bwd", C.c_int,
+     [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p,
+      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+      C.c_void_p]),
     ("gpp_status_string", C.c_char_p, [C.c_int]),
     ("gpp_last_error", C.c_char_p, []),
     ("gpp_version", C.c_int, []),

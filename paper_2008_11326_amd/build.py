@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgpp.so")
-SOURCES = ["gpp_api.hip", "gpp_fwd.hip", "gpp_microbench.hip"]
+SOURCES = ["gpp_api.hip", "gpp_fwd.hip", "gpp_bwd.hip", "gpp_microbench.hip"]
 HEADERS = ["gpp_device.h", "gpp_internal.h"]
 ARCH = "gfx950"
 

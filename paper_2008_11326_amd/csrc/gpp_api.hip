@@ -129,6 +129,52 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in, double *ach
     return GPP_OK;
 }
 
+size_t gpp_sigma_bwd_workspace(const gpp_dims *dims)
+{
+    gpp::Dims32 d;
+    if (check_dims(dims, &d) != GPP_OK) return 0;
+    return gpp::bwd_geometry(d).workspace_bytes;
+}
+
+gpp_status gpp_sigma_bwd(const gpp_dims *dims, const gpp_inputs *in,
+                         const double *grad_achtemp, const double *grad_asxtemp,
+                         double *grad_aqsmtemp, double *grad_aqsntemp, double *grad_I_eps_array,
+                         double *grad_wtilde_array, void *workspace, size_t workspace_bytes,
+                         void *stream)
+{
+    g_last_error[0] = '\0';
+    gpp::Dims32 d;
+    gpp::DevInputs din;
+    gpp_status s;
+    if ((s = check_dims(dims, &d))) return s;
+    if ((s = check_inputs(d, in, &din))) return s;
+    if ((s = check_array("grad_achtemp", grad_achtemp, d.nw, 16)) ||
+        (s = check_array("grad_asxtemp", grad_asxtemp, d.nw, 16)))
+        return s;
+    // optional outputs: NULL skips, otherwise aligned
+    const void *outs[4] = {grad_aqsmtemp, grad_aqsntemp, grad_I_eps_array, grad_wtilde_array};
+    const char *names[4] = {"grad_aqsmtemp", "grad_aqsntemp", "grad_I_eps_array",
+                            "grad_wtilde_array"};
+    for (int k = 0; k < 4; ++k)
+        if (outs[k] && misaligned(outs[k], 16))
+            return fail(GPP_ERR_INVALID, "%s is not 16-byte aligned", names[k]);
+    const size_t need = gpp_sigma_bwd_workspace(dims);
+    if (!workspace || workspace_bytes < need)
+        return fail(GPP_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu%s", need,
+                    workspace_bytes, workspace ? "" : " (NULL)");
+    if (misaligned(workspace, 256))
+        return fail(GPP_ERR_INVALID, "workspace is not 256-byte aligned");
+    gpp::BwdOutputs out{reinterpret_cast<double2 *>(grad_aqsmtemp),
+                        reinterpret_cast<double2 *>(grad_aqsntemp),
+                        reinterpret_cast<double2 *>(grad_I_eps_array),
+                        reinterpret_cast<double2 *>(grad_wtilde_array)};
+    hipError_t e = gpp::launch_bwd(d, din, reinterpret_cast<const double2 *>(grad_achtemp),
+                                   reinterpret_cast<const double2 *>(grad_asxtemp), out,
+                                   workspace, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "gpp_sigma_bwd launch");
+    return GPP_OK;
+}
+
 const char *gpp_status_string(gpp_status s)
 {
     switch (s) {

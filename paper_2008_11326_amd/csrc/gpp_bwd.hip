@@ -1,0 +1,442 @@
+// gpp_bwd.hip -- adjoint of the GPP reduction on gfx950 (fp64, no MFMA).
+//
+// Loss L = sum_w Re(conj(ga[w]) achtemp[w] + conj(gs[w]) asxtemp[w]); the
+// gradient of a complex input z is dL/dRe z + i dL/dIm z (no derivative
+// through the branch).  Nothing is stored by the forward: every term's
+// wdiff, reciprocal and branch are recomputed here.
+//
+// Per (n, p, g), with u_w = conj(1/(x_w - om)) for branch-A terms (else 0)
+// and the exchange quantities of occupied bands (ssx = e sigma,
+// d ssx/d om = e delta):
+//   K  = sum_w ga_w/2 u_w            L  = sum_w x_w ga_w/2 u_w^2
+//   KS = sum_w gs_w conj(sigma_w)    LS = sum_w gs_w conj(delta_w)
+//   Z  = conj(om) K + KS             W  = L + LS
+// the gradients are
+//   dI_eps[p][g]    = vcoul[g]         sum_n conj(M) Z
+//   dwtilde[p][g]   = vcoul[g] conj(e) sum_n conj(M) W
+//   daqsntemp[n][g] = sum_p vcoul[g] conj(e) aqsmtemp[n][p] Z
+//   daqsmtemp[n][p] = sum_g vcoul[g] e aqsntemp[n][g] conj(Z)
+// with M = aqsntemp[n][g] conj(aqsmtemp[n][p]).
+//
+// Kernels: bwd_pairs (lane = g, wave-uniform p, bands serial) writes
+// dwtilde and dI_eps and, per workgroup of 256 rows, partial sums of
+// daqsmtemp; bwd_bands (lane = g, a wave owns kBandTile bands and walks
+// every p) writes daqsntemp; reduce_am sums the daqsmtemp partials in a
+// fixed order and zero-fills columns >= ngpown.  No atomics: results are
+// bitwise reproducible.
+#include "gpp_device.h"
+#include "gpp_internal.h"
+
+namespace gpp {
+
+constexpr int kBwdWaves = 4;
+constexpr int kBwdThreads = kBwdWaves * kWave;
+constexpr int kRowsPerBlock = kBwdWaves * kWave;  // g rows per pairs workgroup
+constexpr int kBwdGroup = 3;                       // bands per batch-inverted group
+constexpr int kChunk = 48;                         // bands per LDS flush (multiple of 3)
+constexpr int kBandTile = 6;                       // bands per bands-kernel wave
+
+// Upstream gradient scaled for the kernels: gh[w] = ga[w]/2 and
+// xgh[w][n] = wx[w][n] ga[w]/2, written once by bwd_prepare.
+__global__ void bwd_prepare(int nb, int nw, const double *__restrict__ wx,
+                            const double2 *__restrict__ ga, double2 *__restrict__ gh,
+                            double2 *__restrict__ xgh)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) gh[i] = make_double2(0.5 * ga[i].x, 0.5 * ga[i].y);
+    if (i < nw * nb) {
+        const int w = i / nb;
+        const double x = wx[i];
+        xgh[i] = make_double2(0.5 * x * ga[w].x, 0.5 * x * ga[w].y);
+    }
+}
+
+// Exchange term of an occupied band: ssx = e sigma, d ssx/d om = e delta.
+__device__ inline void sx_sigma_delta(double x, double a, double b, double wi2, double wtr,
+                                      double thr, cplx &sigma, cplx &delta)
+{
+    const cplx om = cmake(a, b);
+    const double dr = x - a;
+    const double wd = fma(dr, dr, wi2);
+    const cplx d = cmake(dr, -b);    // x - om
+    const cplx s = cmake(x + a, b);  // x + om
+    if (wd > thr) {                  // A: sigma = om^2/(d s), delta = 2 om x^2/(d s)^2
+        const cplx ds = cmul(d, s);
+        sigma = cdiv(cmul(om, om), ds);
+        delta = cdiv(cscale(2.0 * x * x, om), cmul(ds, ds));
+    } else if (branch_b_holds(wtr, wd)) {  // B: sigma = -om/(2s), delta = -x/(2 s^2)
+        const cplx s2 = cscale(-2.0, s);
+        sigma = cdiv(om, s2);
+        delta = cdiv(cmake(x, 0.0), cmul(s2, s));
+    } else {
+        sigma = delta = cmake(0.0, 0.0);
+    }
+}
+
+// K (and, with WANT_L, L) of BU bands starting at band n for one lane:
+// batch-inverted reciprocals over the BU*NW terms, masked to branch A.
+template <int NW, int BU, bool WANT_L>
+__device__ __forceinline__ void ch_bands_kl(int n, int nb, const double *__restrict__ wx,
+                                            const double2 *__restrict__ gh,
+                                            const double2 *__restrict__ xgh, double a, double b,
+                                            double wi2, double thr, cplx (&K)[BU], cplx (&L)[BU])
+{
+    constexpr int Kt = BU * NW;
+    double xs[Kt], dc[Kt], drs[Kt], r[Kt];
+    bool isA[Kt];
+#pragma unroll
+    for (int u = 0; u < BU; ++u)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
+#pragma unroll
+    for (int k = 0; k < Kt; ++k) {
+        drs[k] = xs[k] - a;
+        const double wd = fma(drs[k], drs[k], wi2);
+        isA[k] = wd > thr;
+        dc[k] = fmax(wd, kLimitTwo);
+    }
+    batch_reciprocal<Kt>(dc, r);
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+        K[u] = L[u] = cmake(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int k = u * NW + w;
+            const double re = mask_keep(isA[k], r[k]);
+            const cplx uu = cmake(drs[k] * re, -b * re);  // conj(1/(x - om))
+            cmac(K[u], cload(gh + w), uu);
+            if (WANT_L) cmac(L[u], cload(xgh + (size_t)w * nb + n + u), cmul(uu, uu));
+        }
+    }
+}
+
+// KS, LS of one occupied band n for one lane.
+template <int NW>
+__device__ __forceinline__ void sx_band_kl(int n, int nb, const double *__restrict__ wx,
+                                           const double2 *__restrict__ gs, double a, double b,
+                                           double wi2, double wtr, double thr, cplx &KS, cplx &LS)
+{
+    KS = LS = cmake(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        cplx sigma, delta;
+        sx_sigma_delta(wx[(size_t)w * nb + n], a, b, wi2, wtr, thr, sigma, delta);
+        const cplx g = cload(gs + w);
+        cmac(KS, g, cmake(sigma.re, -sigma.im));
+        cmac(LS, g, cmake(delta.re, -delta.im));
+    }
+}
+
+struct PairState {
+    double a, b, wi2, wtr, thr;
+    cplx om, e, ve;  // ve = vcoul[g] e (0 for rows beyond ncouls)
+};
+
+__device__ __forceinline__ PairState load_pair(const double2 *wt, const double2 *ieps,
+                                               const double *vcoul, int p, int ng, int gc,
+                                               bool valid)
+{
+    PairState s;
+    s.om = cload(wt + (size_t)p * ng + gc);
+    s.e = cload(ieps + (size_t)p * ng + gc);
+    s.a = s.om.re;
+    s.b = s.om.im;
+    s.wi2 = s.b * s.b;
+    s.wtr = fma(s.a, s.a, s.wi2);
+    s.thr = branch_a_threshold(s.wtr);
+    s.ve = cscale(valid ? vcoul[gc] : 0.0, s.e);
+    return s;
+}
+
+// ---- pairs kernel: dwtilde, dI_eps and daqsmtemp partials -----------------
+template <int NW>
+__global__ void __launch_bounds__(kBwdThreads)
+bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restrict__ aqsm,
+          const double2 *__restrict__ aqsn, const double2 *__restrict__ ieps,
+          const double2 *__restrict__ wt, const double *__restrict__ vcoul,
+          const double *__restrict__ wx, const double2 *__restrict__ gh,
+          const double2 *__restrict__ xgh, const double2 *__restrict__ gs,
+          double2 *__restrict__ grad_wt, double2 *__restrict__ grad_ieps,
+          double2 *__restrict__ am_part)
+{
+    __shared__ double red[kBwdWaves][kChunk][2];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const long blk = xcd_remap(blockIdx.x, gridDim.x);
+    if (blk >= nblocks) return;  // whole workgroup leaves together
+    // p fastest: concurrently resident workgroups share one 256-row block
+    const int gb = (int)(blk / np);
+    const int p = (int)(blk - (long)gb * np);
+    const int g = gb * kRowsPerBlock + wid * kWave + lane;
+    const bool valid = g < ng;
+    const int gc = valid ? g : ng - 1;
+    const PairState ps = load_pair(wt, ieps, vcoul, p, ng, gc, valid);
+    const cplx cw = cmake(ps.om.re, -ps.om.im);  // conj(om)
+    const double2 *am_col = aqsm + p;
+    const uint32_t goff = (uint32_t)gc * (uint32_t)sizeof(double2);
+
+    cplx Ge = cmake(0.0, 0.0), Gw = cmake(0.0, 0.0);
+    for (int c0 = 0; c0 < nb; c0 += kChunk) {
+        const int c1 = c0 + kChunk < nb ? c0 + kChunk : nb;
+        int n = c0;
+        while (n < c1) {
+            // bands n .. n+cnt-1 form one batch-inverted group
+            const bool occ = n < nv;
+            const int cnt = (!occ && n + kBwdGroup <= c1 && n + kBwdGroup <= nb) ? kBwdGroup : 1;
+            cplx K[kBwdGroup], L[kBwdGroup];
+            if (cnt == kBwdGroup) {
+                ch_bands_kl<NW, kBwdGroup, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2,
+                                                 ps.thr, K, L);
+            } else {
+                cplx K1[1], L1[1];
+                ch_bands_kl<NW, 1, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr, K1, L1);
+                K[0] = K1[0];
+                L[0] = L1[0];
+            }
+#pragma unroll
+            for (int u = 0; u < kBwdGroup; ++u) {
+                if (u >= cnt) break;  // wave-uniform
+                const int nn = n + u;
+                cplx Z = cmul(cw, K[u]);
+                cplx W = L[u];
+                if (nn < nv) {
+                    cplx KS, LS;
+                    sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS, LS);
+                    Z = cadd(Z, KS);
+                    W = cadd(W, LS);
+                }
+                const cplx an = load_row_elem(aqsn + (size_t)nn * ng, ng, goff);
+                const cplx am = cload(am_col + (size_t)nn * ng);
+                const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
+                cmac(Ge, cM, Z);
+                cmac(Gw, cM, W);
+                if (am_part) {
+                    // this lane's term of daqsmtemp[nn][p]: ve an conj(Z)
+                    const cplx t = cmul(ps.ve, cmul_conj(an, Z));
+                    const double sr = wave_sum(t.re), si = wave_sum(t.im);
+                    if (lane == 0) {
+                        red[wid][nn - c0][0] = sr;
+                        red[wid][nn - c0][1] = si;
+                    }
+                }
+            }
+            n += cnt;
+        }
+        if (am_part) {
+            __syncthreads();
+            const int t = threadIdx.x;
+            if (t < 2 * (c1 - c0)) {
+                const int j = t >> 1, c = t & 1;
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < kBwdWaves; ++k) s += red[k][j][c];
+                double *dst = reinterpret_cast<double *>(
+                    am_part + ((size_t)gb * nb + c0 + j) * np + p);
+                dst[c] = s;
+            }
+            __syncthreads();
+        }
+    }
+    if (valid) {
+        const double v = vcoul[g];
+        const size_t idx = (size_t)p * ng + g;
+        if (grad_ieps) {
+            const cplx r = cscale(v, Ge);
+            grad_ieps[idx] = make_double2(r.re, r.im);
+        }
+        if (grad_wt) {
+            const cplx r = cscale(v, cmul(cmake(ps.e.re, -ps.e.im), Gw));
+            grad_wt[idx] = make_double2(r.re, r.im);
+        }
+    }
+}
+
+// ---- bands kernel: daqsntemp --------------------------------------------
+template <int NW>
+__global__ void __launch_bounds__(kBwdThreads)
+bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
+          const double2 *__restrict__ aqsm, const double2 *__restrict__ ieps,
+          const double2 *__restrict__ wt, const double *__restrict__ vcoul,
+          const double *__restrict__ wx, const double2 *__restrict__ gh,
+          const double2 *__restrict__ gs, double2 *__restrict__ grad_an)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const long tile = (long)xcd_remap(blockIdx.x, gridDim.x) * kBwdWaves + wid;
+    if (tile >= ntiles) return;  // wave-uniform; no barriers below
+    // band tile fastest: neighbouring waves share the g rows of wtilde/I_eps
+    const int gt = (int)(tile / nbt);
+    const int n0 = (int)(tile - (long)gt * nbt) * kBandTile;
+    const int g = gt * kWave + lane;
+    const bool valid = g < ng;
+    const int gc = valid ? g : ng - 1;
+
+    cplx acc[kBandTile];
+#pragma unroll
+    for (int u = 0; u < kBandTile; ++u) acc[u] = cmake(0.0, 0.0);
+
+    for (int p = 0; p < np; ++p) {
+        const PairState ps = load_pair(wt, ieps, vcoul, p, ng, gc, valid);
+        const cplx cw = cmake(ps.om.re, -ps.om.im);
+        const cplx vce = cmake(ps.ve.re, -ps.ve.im);  // vcoul conj(e)
+#pragma unroll
+        for (int u0 = 0; u0 < kBandTile; u0 += kBwdGroup) {
+            const int n = n0 + u0;
+            if (n >= nb) break;  // wave-uniform
+            cplx K[kBwdGroup], L[kBwdGroup];
+            const bool full = n + kBwdGroup <= nb && n >= nv;
+            if (full) {
+                ch_bands_kl<NW, kBwdGroup, false>(n, nb, wx, gh, nullptr, ps.a, ps.b, ps.wi2,
+                                                  ps.thr, K, L);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kBwdGroup; ++u) {
+                    K[u] = cmake(0.0, 0.0);
+                    if (n + u < nb) {
+                        cplx K1[1], L1[1];
+                        ch_bands_kl<NW, 1, false>(n + u, nb, wx, gh, nullptr, ps.a, ps.b,
+                                                  ps.wi2, ps.thr, K1, L1);
+                        K[u] = K1[0];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBwdGroup; ++u) {
+                const int nn = n + u;
+                if (nn < nb) {
+                    cplx Z = cmul(cw, K[u]);
+                    if (nn < nv) {
+                        cplx KS, LS;
+                        sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS, LS);
+                        Z = cadd(Z, KS);
+                    }
+                    const cplx am = cload(aqsm + (size_t)nn * ng + p);
+                    cmac(acc[u0 + u], am, cmul(vce, Z));
+                }
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int u = 0; u < kBandTile; ++u) {
+            const int n = n0 + u;
+            if (n < nb) grad_an[(size_t)n * ng + g] = make_double2(acc[u].re, acc[u].im);
+        }
+    }
+}
+
+// daqsmtemp[n][p] = sum over row blocks of the partials (p < np), 0 for
+// columns np..ncouls-1.  One thread per output element, fixed order.
+__global__ void reduce_am(int nb, int ng, int np, int ngb, const double2 *__restrict__ part,
+                          double2 *__restrict__ grad_am)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)nb * ng) return;
+    const int n = (int)(i / ng), col = (int)(i - (long)n * ng);
+    double re = 0.0, im = 0.0;
+    if (col < np) {
+        for (int b = 0; b < ngb; ++b) {
+            const double2 v = part[((size_t)b * nb + n) * np + col];
+            re += v.x;
+            im += v.y;
+        }
+    }
+    grad_am[i] = make_double2(re, im);
+}
+
+__global__ void fill_zero_n(double2 *a, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = make_double2(0.0, 0.0);
+}
+
+BwdGeometry bwd_geometry(const Dims32 &d)
+{
+    BwdGeometry geo{};
+    geo.gh_elems = d.nw;
+    geo.xgh_elems = (size_t)d.nw * d.nb;
+    if (d.nb > 0 && d.ng > 0 && d.np > 0) {
+        geo.ngb = (d.ng + kRowsPerBlock - 1) / kRowsPerBlock;
+        geo.pair_blocks = (long)geo.ngb * d.np;
+        geo.nbt = (d.nb + kBandTile - 1) / kBandTile;
+        geo.band_tiles = (long)((d.ng + kWave - 1) / kWave) * geo.nbt;
+        geo.band_blocks = (geo.band_tiles + kBwdWaves - 1) / kBwdWaves;
+        geo.am_part_elems = (size_t)geo.ngb * d.nb * d.np;
+    }
+    // complex elements, each 16 bytes; sections 256-byte aligned
+    auto up = [](size_t e) { return (e * sizeof(double2) + 255) / 256 * 256; };
+    geo.workspace_bytes = up(geo.gh_elems) + up(geo.xgh_elems) + up(geo.am_part_elems);
+    if (geo.workspace_bytes == 0) geo.workspace_bytes = 256;
+    return geo;
+}
+
+template <int NW>
+static hipError_t launch_bwd_nw(const Dims32 &d, const BwdGeometry &geo, const DevInputs &in,
+                                const double2 *ga, const double2 *gs, const BwdOutputs &out,
+                                char *ws, hipStream_t st)
+{
+    auto up = [](size_t e) { return (e * sizeof(double2) + 255) / 256 * 256; };
+    double2 *gh = reinterpret_cast<double2 *>(ws);
+    double2 *xgh = reinterpret_cast<double2 *>(ws + up(geo.gh_elems));
+    double2 *am_part = reinterpret_cast<double2 *>(ws + up(geo.gh_elems) + up(geo.xgh_elems));
+    const int prep = d.nw * d.nb > d.nw ? d.nw * d.nb : d.nw;
+    hipLaunchKernelGGL(bwd_prepare, dim3((prep + 255) / 256), dim3(256), 0, st, d.nb, d.nw,
+                       in.wx, ga, gh, xgh);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bool want_pairs = out.grad_wt || out.grad_ieps || out.grad_am;
+    if (want_pairs) {
+        hipLaunchKernelGGL(bwd_pairs<NW>, dim3((unsigned)geo.pair_blocks), dim3(kBwdThreads), 0,
+                           st, d.nb, d.nv, d.ng, d.np, geo.pair_blocks, in.aqsm, in.aqsn,
+                           in.ieps, in.wt, in.vcoul, in.wx, gh, xgh, gs, out.grad_wt,
+                           out.grad_ieps, out.grad_am ? am_part : nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (out.grad_am) {
+        const long n = (long)d.nb * d.ng;
+        hipLaunchKernelGGL(reduce_am, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d.nb,
+                           d.ng, d.np, geo.ngb, am_part, out.grad_am);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (out.grad_an) {
+        hipLaunchKernelGGL(bwd_bands<NW>, dim3((unsigned)geo.band_blocks), dim3(kBwdThreads), 0,
+                           st, d.nb, d.nv, d.ng, d.np, geo.band_tiles, geo.nbt, in.aqsm, in.ieps,
+                           in.wt, in.vcoul, in.wx, gh, gs, out.grad_an);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_bwd(const Dims32 &d, const DevInputs &in, const double2 *ga,
+                      const double2 *gs, const BwdOutputs &out, void *workspace, hipStream_t st)
+{
+    const BwdGeometry geo = bwd_geometry(d);
+    if (geo.pair_blocks == 0) {
+        // an empty sum: every requested gradient is zero
+        const long npg = (long)d.np * d.ng, nbg = (long)d.nb * d.ng;
+        double2 *outs[4] = {out.grad_wt, out.grad_ieps, out.grad_an, out.grad_am};
+        const long lens[4] = {npg, npg, nbg, nbg};
+        for (int k = 0; k < 4; ++k) {
+            if (!outs[k] || lens[k] == 0) continue;
+            hipLaunchKernelGGL(fill_zero_n, dim3((unsigned)((lens[k] + 255) / 256)), dim3(256), 0,
+                               st, outs[k], lens[k]);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    char *ws = static_cast<char *>(workspace);
+    switch (d.nw) {
+    case 1: return launch_bwd_nw<1>(d, geo, in, ga, gs, out, ws, st);
+    case 2: return launch_bwd_nw<2>(d, geo, in, ga, gs, out, ws, st);
+    case 3: return launch_bwd_nw<3>(d, geo, in, ga, gs, out, ws, st);
+    case 4: return launch_bwd_nw<4>(d, geo, in, ga, gs, out, ws, st);
+    case 5: return launch_bwd_nw<5>(d, geo, in, ga, gs, out, ws, st);
+    case 6: return launch_bwd_nw<6>(d, geo, in, ga, gs, out, ws, st);
+    case 7: return launch_bwd_nw<7>(d, geo, in, ga, gs, out, ws, st);
+    case 8: return launch_bwd_nw<8>(d, geo, in, ga, gs, out, ws, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gpp

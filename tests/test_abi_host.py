@@ -124,3 +124,37 @@ def test_python_binding_rejects_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def _bwd(lib, dims, ins, ga=FAKE + 0x900000, gs=FAKE + 0x900100, outs=(0, 0, 0, 0),
+         ws=FAKE + 0xA00000, ws_bytes=None):
+    need = lib.gpp_sigma_bwd_workspace(C.byref(dims))
+    ws_bytes = need if ws_bytes is None else ws_bytes
+    return lib.gpp_sigma_bwd(C.byref(dims), C.byref(ins), C.c_void_p(ga), C.c_void_p(gs),
+                             *[C.c_void_p(o) for o in outs], C.c_void_p(ws), ws_bytes,
+                             None)
+
+
+def test_bwd_validation(lib):
+    d = _dims()
+    assert _bwd(lib, _dims(nv=9), _inputs()) == 1
+    assert _bwd(lib, d, _inputs(aqsntemp=0)) == 1
+    assert _bwd(lib, d, _inputs(), ga=0) == 1
+    assert "grad_achtemp" in lib.gpp_last_error().decode()
+    assert _bwd(lib, d, _inputs(), gs=FAKE + 8) == 1
+    assert _bwd(lib, d, _inputs(), outs=(FAKE + 8, 0, 0, 0)) == 1
+    assert "grad_aqsmtemp" in lib.gpp_last_error().decode()
+    assert _bwd(lib, d, _inputs(), ws=0) == 4
+    need = lib.gpp_sigma_bwd_workspace(C.byref(d))
+    assert need > 0
+    assert _bwd(lib, d, _inputs(), ws_bytes=need - 1) == 4
+    assert _bwd(lib, d, _inputs(), ws=FAKE + 0xA00010) == 1
+    assert "256-byte" in lib.gpp_last_error().decode()
+
+
+def test_bwd_workspace_grows_with_rows_bands_columns(lib):
+    a = lib.gpp_sigma_bwd_workspace(C.byref(_dims(nb=8, ng=256, npw=10)))
+    b = lib.gpp_sigma_bwd_workspace(C.byref(_dims(nb=8, ng=512, npw=10)))
+    c = lib.gpp_sigma_bwd_workspace(C.byref(_dims(nb=16, ng=512, npw=10)))
+    assert 0 < a < b < c
+    assert lib.gpp_sigma_bwd_workspace(None) == 0

@@ -1,0 +1,191 @@
+"""GPU parity of the adjoint (gpp_sigma_bwd and the GppSigma autograd
+Function) against the oracle's analytic gradient and against central finite
+differences of the GPU forward.
+
+Loss L = sum_w Re(conj(ga[w]) achtemp[w] + conj(gs[w]) asxtemp[w]) with a
+random complex unit-norm upstream gradient; gradients are dL/dRe z +
+i dL/dIm z.  Per-entry bar: |gpu - oracle| <= 1e-12 |oracle| + 1e-12 max|oracle|
+(an absolute floor relative to the array's largest gradient entry).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11326_amd import inputs as I
+from tests.gpu_helpers import say, to_device
+
+pytestmark = pytest.mark.gpu
+
+ARRAYS = ("aqsmtemp", "aqsntemp", "I_eps_array", "wtilde_array")
+
+
+@pytest.fixture(scope="module")
+def gpp():
+    import paper_2008_11326_amd as gpp
+    from paper_2008_11326_amd import _lib
+    _lib.load()
+    return gpp
+
+
+def gpu_grads(gpp, prob, ga, gs, want=(True, True, True, True)):
+    import torch
+    d = to_device(prob)
+    t = lambda z: torch.from_numpy(np.ascontiguousarray(z)).to("cuda:0")
+    out = gpp.sigma_bwd(**d, nvband=prob.dims.nvband, grad_achtemp=t(ga),
+                        grad_asxtemp=t(gs), want=want)
+    torch.cuda.synchronize()
+    return {name: (o.cpu().numpy() if o is not None else None)
+            for name, o in zip(ARRAYS, out)}
+
+
+def check_entries(name, got, prob, ga, gs, idx):
+    ref = oracle.grad_entries(prob, ga, gs, name, idx)
+    vals = np.array([got[i, j] for i, j in idx])
+    floor = 1e-12 * max(np.max(np.abs(ref)), 1e-300)
+    err = np.abs(vals - ref)
+    bad = err > 1e-12 * np.abs(ref) + floor
+    assert not np.any(bad), (name, idx[bad][:5], vals[bad][:5], ref[bad][:5])
+    return float(np.max(err / (np.abs(ref) + floor)))
+
+
+def all_entries(rows, cols):
+    return np.array([(i, j) for i in range(rows) for j in range(cols)], dtype=np.int64)
+
+
+@pytest.mark.parametrize("shape,poles", [
+    ((6, 2, 100, 5, 3), 0.0), ((5, 2, 64, 3, 3), 0.2), ((7, 7, 130, 4, 3), 0.1),
+    ((4, 0, 65, 3, 3), 0.0), ((8, 3, 257, 2, 2), 0.0), ((1, 1, 1, 1, 1), 0.0),
+    ((10, 2, 70, 3, 5), 0.0), ((13, 2, 300, 2, 8), 0.1),
+])
+def test_every_entry_small(gpp, shape, poles):
+    prob = I.make_problem(I.Dims(*shape), sum(shape) + 3, poles)
+    rng = np.random.default_rng(7)
+    ga, gs = I.make_upstream_grad(prob.dims.nfreq, rng)
+    say(f"[bwd] small {shape} poles={poles}")
+    g = gpu_grads(gpp, prob, ga, gs)
+    nb, _, ng, npw, _ = prob.dims.as_tuple()
+    check_entries("aqsmtemp", g["aqsmtemp"], prob, ga, gs, all_entries(nb, ng))
+    check_entries("aqsntemp", g["aqsntemp"], prob, ga, gs, all_entries(nb, ng))
+    check_entries("I_eps_array", g["I_eps_array"], prob, ga, gs, all_entries(npw, ng))
+    check_entries("wtilde_array", g["wtilde_array"], prob, ga, gs, all_entries(npw, ng))
+    assert np.all(g["aqsmtemp"][:, npw:] == 0)
+
+
+def test_skipped_outputs_and_determinism(gpp):
+    prob = I.make_problem(I.Dims(9, 2, 200, 6, 3), 5)
+    ga, gs = I.make_upstream_grad(3, np.random.default_rng(1))
+    full = gpu_grads(gpp, prob, ga, gs)
+    again = gpu_grads(gpp, prob, ga, gs)
+    part = gpu_grads(gpp, prob, ga, gs, want=(False, True, False, True))
+    for name in ARRAYS:
+        assert np.array_equal(full[name], again[name])
+    assert part["aqsmtemp"] is None and part["I_eps_array"] is None
+    assert np.array_equal(part["aqsntemp"], full["aqsntemp"])
+    assert np.array_equal(part["wtilde_array"], full["wtilde_array"])
+
+
+def test_empty_dimensions(gpp):
+    for dims in (I.Dims(0, 0, 64, 4, 3), I.Dims(4, 1, 64, 0, 3)):
+        prob = I.make_problem(dims, 1)
+        ga, gs = I.make_upstream_grad(dims.nfreq, np.random.default_rng(0))
+        g = gpu_grads(gpp, prob, ga, gs)
+        for name in ARRAYS:
+            assert np.all(g[name] == 0)
+
+
+@pytest.fixture(scope="module")
+def adjoint_case():
+    wl = I.WORKLOADS["adjoint"]
+    say(f"[bwd] generating {wl.name}")
+    prob = I.make_problem(wl.dims, wl.seed)
+    rng = np.random.default_rng([wl.seed, 1])
+    ga, gs = I.make_upstream_grad(wl.dims.nfreq, rng)
+    entries = I.make_fd_entries(wl.dims, rng, count=1000)
+    return prob, ga, gs, entries
+
+
+def test_adjoint_workload_against_oracle(gpp, adjoint_case):
+    """1000 random entries per array at the adjoint workload's full size."""
+    prob, ga, gs, entries = adjoint_case
+    say("[bwd] adjoint workload: GPU gradients")
+    g = gpu_grads(gpp, prob, ga, gs)
+    worst = {}
+    for name in ARRAYS:
+        worst[name] = check_entries(name, g[name], prob, ga, gs, entries[name])
+    say(f"[bwd] adjoint workload worst scaled error {worst}")
+    npw = prob.dims.ngpown
+    assert np.all(g["aqsmtemp"][:, npw:] == 0)
+
+
+def test_adjoint_workload_finite_differences(gpp, adjoint_case):
+    """Central differences (h = 1e-6) of the GPU forward on 50 entries per
+    array; stencils that move a touched term across a branch boundary are
+    skipped (checked with the oracle's branch codes)."""
+    import torch
+    prob, ga, gs, entries = adjoint_case
+    d = to_device(prob)
+    nv = prob.dims.nvband
+    gat = torch.from_numpy(ga).to("cuda:0")
+    gst = torch.from_numpy(gs).to("cuda:0")
+    grads = gpu_grads(gpp, prob, ga, gs)
+    h = 1e-6
+
+    def loss():
+        ach, asx = gpp.sigma_fwd(**d, nvband=nv)
+        return float(torch.sum((torch.conj(gat) * ach + torch.conj(gst) * asx).real))
+
+    checked = 0
+    for name in ARRAYS:
+        arr = d[name]
+        for i, j in entries[name][:50]:
+            z0 = complex(arr[i, j].item())
+            _, b0 = oracle.slice_loss(prob, ga, gs, name, i, j, z0)
+            fd = []
+            ok = True
+            for step in (h, 1j * h):
+                vals = []
+                for sgn in (1, -1):
+                    _, b = oracle.slice_loss(prob, ga, gs, name, i, j, z0 + sgn * step)
+                    ok &= np.array_equal(b, b0)
+                    arr[i, j] = z0 + sgn * step
+                    vals.append(loss())
+                arr[i, j] = z0
+                fd.append((vals[0] - vals[1]) / (2 * h))
+            if not ok:
+                continue
+            checked += 1
+            got = grads[name][i, j]
+            fdz = complex(fd[0], fd[1])
+            scale = max(abs(got), 1e-3 * np.max(np.abs(grads[name])))
+            assert abs(fdz - got) <= 1e-4 * scale, (name, i, j, got, fdz)
+    assert checked >= 190
+
+
+def test_autograd_function_matches_direct_call(gpp):
+    import torch
+    prob = I.make_problem(I.Dims(12, 2, 300, 7, 3), 11, 0.05)
+    d = to_device(prob)
+    leaves = {k: v.clone().requires_grad_(k in ARRAYS) for k, v in d.items()}
+    ach, asx = gpp.sigma(**leaves, nvband=2)
+    ga, gs = I.make_upstream_grad(3, np.random.default_rng(9))
+    gat = torch.from_numpy(ga).to("cuda:0")
+    gst = torch.from_numpy(gs).to("cuda:0")
+    L = torch.sum((torch.conj(gat) * ach + torch.conj(gst) * asx).real)
+    L.backward()
+    direct = gpu_grads(gpp, prob, ga, gs)
+    for name in ARRAYS:
+        assert np.array_equal(leaves[name].grad.cpu().numpy(), direct[name])
+    assert leaves["vcoul"].grad is None and leaves["wx_array"].grad is None
+
+
+def test_autograd_gradcheck_tiny(gpp):
+    """torch.autograd.gradcheck (its own finite differences, complex inputs)
+    on a tiny problem whose terms sit far from branch boundaries."""
+    import torch
+    prob = I.make_problem(I.Dims(3, 1, 5, 2, 2), 2)
+    prob.wx_array[:] = np.array([[-1.5, -1.2, -1.0], [2.9, 3.1, 3.3]])
+    d = to_device(prob)
+    args = [d[k].clone().requires_grad_(k in ARRAYS) for k in
+            ("aqsmtemp", "aqsntemp", "I_eps_array", "wtilde_array", "vcoul", "wx_array")]
+    fn = lambda *a: gpp.sigma(*a, 1)
+    assert torch.autograd.gradcheck(fn, args, eps=1e-6, atol=1e-7, rtol=1e-6)

@@ -37,7 +37,7 @@ def log(msg):
 def fwd_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gpp_fwd.hip", "gpp_device.h"):
+    for f in ("gpp_fwd.hip", "gpp_fwd_tile.h", "gpp_device.h"):
         with open(os.path.join(ROOT, "paper_2008_11326_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,6 +84,86 @@ def cpu_baseline(prob, target_seconds):
     }
 
 
+def timed_ms(fn, stream, reps):
+    """Average milliseconds of fn() over reps runs, HIP events on `stream`."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def adjoint_leg(gpp, I, stream, reps=5):
+    """Forward and hand-written adjoint on the adjoint workload."""
+    import numpy as np
+    import torch
+    wl = I.WORKLOADS["adjoint"]
+    d = wl.dims
+    prob = I.make_problem(d, wl.seed)
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in prob.arrays()]
+    ga, gs = I.make_upstream_grad(d.nfreq, np.random.default_rng([wl.seed, 1]))
+    ga = torch.from_numpy(ga).to(dev)
+    gs = torch.from_numpy(gs).to(dev)
+    ws = torch.empty(gpp.bwd_workspace_bytes(*d.as_tuple()), dtype=torch.uint8, device=dev)
+    fwd = timed_ms(lambda: gpp.sigma_fwd(*t, nvband=d.nvband, stream=stream.cuda_stream),
+                   stream, reps)
+    bwd = timed_ms(lambda: gpp.sigma_bwd(*t, d.nvband, ga, gs, workspace=ws,
+                                         stream=stream.cuda_stream), stream, reps)
+    terms = d.ch_terms + d.sx_terms
+    return {"workload": wl.name, "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
+            "bwd_over_fwd_time": round(bwd / fwd, 3),
+            "bwd_terms_per_s": terms / (bwd * 1e-3),
+            "bwd_throughput_vs_plain": round(fwd / bwd, 4),
+            "grads": "aqsmtemp, aqsntemp, I_eps_array, wtilde_array"}
+
+
+def batched_leg(gpp, I, stream, reps=3):
+    """64 uneven states in one persistent graph-replayed launch vs 64
+    sequential plain forwards on the same device-resident inputs."""
+    import torch
+    dims = I.batched_dims()
+    states = [I.make_problem_device(dd, 1000 + k) for k, dd in enumerate(dims)]
+    plan = gpp.Plan([dd.as_tuple() for dd in dims])
+    nw = dims[0].nfreq
+    dev = torch.device("cuda:0")
+    out = (torch.empty((len(dims), nw), dtype=torch.complex128, device=dev),
+           torch.empty((len(dims), nw), dtype=torch.complex128, device=dev))
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    gpp.sigma_batched(plan, states, out=out, workspace=ws, stream=stream.cuda_stream)
+    torch.cuda.synchronize()  # first call tunes (or reads the cache) and captures
+    bat = timed_ms(lambda: gpp.sigma_batched(plan, states, out=out, workspace=ws,
+                                             stream=stream.cuda_stream), stream, reps)
+    plain_out = []
+
+    def plain():
+        plain_out.clear()
+        for st, dd in zip(states, dims):
+            plain_out.append(gpp.sigma_fwd(**st, nvband=dd.nvband, stream=stream.cuda_stream))
+    seq = timed_ms(plain, stream, 1)
+    worst = 0.0
+    for k, (a, x) in enumerate(plain_out):
+        for got, ref in ((out[0][k], a), (out[1][k], x)):
+            worst = max(worst, float(torch.max(torch.abs(got - ref) / torch.abs(ref))))
+    terms = sum(dd.ch_terms + dd.sx_terms for dd in dims)
+    info = plan.info()
+    plan.close()
+    return {"states": len(dims), "terms": terms, "batched_ms": round(bat, 3),
+            "sequential_plain_ms": round(seq, 3),
+            "batched_tflops": round(FLOP_PER_TERM * terms / (bat * 1e-3) / 1e12, 3),
+            "speedup_vs_sequential_plain": round(seq / bat, 4),
+            "max_rel_diff_vs_plain": worst,
+            "plan": {k: info[k] for k in ("bands_per_group", "schedule_order", "schedule",
+                                           "waves", "candidates", "from_cache")},
+            "data": "synthetic, drawn on the device (same distributions)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +172,8 @@ def main():
     ap.add_argument("--workload", default="si")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint and batched legs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -185,6 +267,14 @@ def main():
         e = max(rel_errors(res[0], gold["ach"], gold["ach_abs_sum"]).max(),
                 rel_errors(res[1], gold["asx"], gold["asx_abs_sum"]).max())
         out["max_rel_err_vs_oracle"] = float(e)
+    if not args.no_extras:
+        del t_in, ws
+        torch.cuda.empty_cache()
+        log("[bench] adjoint leg")
+        out["adjoint"] = adjoint_leg(gpp, I, stream)
+        log("[bench] batched leg")
+        out["batched"] = batched_leg(gpp, I, stream)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded slice")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)

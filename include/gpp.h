@@ -137,6 +137,77 @@ gpp_status gpp_sigma_bwd(const gpp_dims *dims, const gpp_inputs *in,
                          double *grad_I_eps_array, double *grad_wtilde_array,
                          void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- batched forward over many quasiparticle states ------------------- */
+
+#define GPP_MAX_STATES 65536
+
+/* Opaque plan: the states' sizes, the chosen tile variant and schedule,
+ * a device descriptor table and a captured hipGraph. */
+typedef struct gpp_plan gpp_plan;
+
+/*
+ * gpp_plan_create -- plan a batched forward for `nstates` states whose
+ * sizes are dims_host[0..nstates-1] (host array; every state must share
+ * nfreq).  Queries the current device (must be gfx950), sizes the
+ * persistent grid to the kernel's resident capacity, and allocates the
+ * plan's device descriptor table, pinned staging buffer and capture
+ * stream.  The schedule is tuned on the first gpp_sigma_batched call (or
+ * taken from the tuning cache, see below).  *out is NULL on failure.
+ */
+gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan **out);
+
+/* Device workspace bytes gpp_sigma_batched needs with this plan. */
+size_t gpp_plan_workspace(const gpp_plan *plan);
+
+typedef struct {
+    int32_t tuned;            /* 1 once a candidate has been chosen          */
+    int32_t from_cache;       /* 1 if the choice came from the tuning cache  */
+    int32_t bands_per_group;  /* tile variant of the chosen candidate        */
+    int32_t schedule_order;   /* 0 = caller order, 1 = longest tiles first   */
+    int32_t workgroups;       /* persistent workgroups (4 waves each)        */
+    int32_t waves;
+    int32_t candidates;       /* size of the search space                    */
+    int32_t schedule;         /* 0 = global round-robin, 1 = one contiguous
+                                 chunk of the tile list per XCD, 2 = work
+                                 queue of 4-tile chunks, 3 = one such queue
+                                 per XCD (own region first, then stealing)   */
+    int64_t total_tiles;      /* 64-row wave tiles over all states           */
+    double tuned_ms;          /* measured time of the chosen candidate       */
+} gpp_plan_info;
+
+/* Fill *info (host) with the plan's current choice. */
+gpp_status gpp_plan_get_info(const gpp_plan *plan, gpp_plan_info *info);
+
+/*
+ * gpp_sigma_batched -- for every state s, the reduction of gpp_sigma_fwd
+ * (Sec. II-A) over inputs_host[s] (host array of device-pointer sets),
+ * all states in one persistent launch followed by one per-state reduction,
+ * replayed from a hipGraph.
+ *   achtemp, asxtemp: device, complex [nstates][nfreq], overwritten
+ *   workspace:        device, >= gpp_plan_workspace(plan) bytes, 256-byte
+ *                     aligned
+ * First call (tuning): unless the cache holds a choice for these sizes on
+ * this architecture, each candidate (tile variant x state order x
+ * tile-to-wave schedule) runs
+ * twice on the caller's inputs, timed with events (the call synchronises
+ * `stream` then), and the fastest is kept and saved to the cache file
+ * $GPP_TUNE_CACHE (default $XDG_CACHE_HOME/gpp/tune.json, else
+ * ~/.cache/gpp/tune.json; unreadable or corrupt files are ignored).
+ * GPP_AUTOTUNE=off skips timing and uses the default candidate;
+ * GPP_TUNE_VERBOSE=1 prints every candidate's time to stderr.
+ * Every call: the descriptor table is re-uploaded (async, on `stream`)
+ * only when an input pointer changed; the graph is re-captured only when
+ * achtemp, asxtemp or workspace changed.  Calls on one plan must be
+ * ordered (one stream, or externally synchronised); `stream` must not be
+ * capturing.  Results are deterministic for a fixed plan choice.
+ */
+gpp_status gpp_sigma_batched(gpp_plan *plan, const gpp_inputs *inputs_host,
+                             double *achtemp, double *asxtemp, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/* Release a plan.  Work using it must have completed. */
+void gpp_plan_destroy(gpp_plan *plan);
+
 /* Static string for a status code. */
 const char *gpp_status_string(gpp_status status);
 

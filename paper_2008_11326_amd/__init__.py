@@ -8,6 +8,8 @@ memory and the current stream) into that ABI.
                          vcoul, wx_array, nvband)
     grads = sigma_bwd(..., grad_achtemp, grad_asxtemp)   # adjoint
     ach, asx = sigma(...)            # differentiable (GppSigma autograd.Function)
+    plan = Plan([dims_0, dims_1, ...])          # many states, one launch
+    ach, asx = sigma_batched(plan, [state_0_tensors, state_1_tensors, ...])
 
 Layouts (row-major, last index fastest): aqsmtemp/aqsntemp complex128
 [number_bands, ncouls]; I_eps_array/wtilde_array complex128 [ngpown, ncouls];
@@ -21,8 +23,9 @@ import ctypes as C
 from . import _lib
 from ._lib import GppError, MAX_NFREQ
 
-__all__ = ["sigma_fwd", "sigma_bwd", "sigma", "GppSigma", "fwd_workspace_bytes",
-           "bwd_workspace_bytes", "GppError", "MAX_NFREQ", "library_path"]
+__all__ = ["sigma_fwd", "sigma_bwd", "sigma", "GppSigma", "Plan", "sigma_batched",
+           "fwd_workspace_bytes", "bwd_workspace_bytes", "GppError", "MAX_NFREQ",
+           "library_path"]
 
 
 def library_path() -> str:
@@ -202,3 +205,82 @@ def sigma(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array, nvband
     """Differentiable (achtemp, asxtemp) through GppSigma."""
     return __getattr__("GppSigma").apply(aqsmtemp, aqsntemp, I_eps_array,
                                          wtilde_array, vcoul, wx_array, nvband)
+
+
+class Plan:
+    """Batched-forward plan (gpp_plan_create): the states' sizes as
+    (number_bands, nvband, ncouls, ngpown, nfreq) tuples.  Create it with
+    the target device current; release with close() (or let it be
+    collected)."""
+
+    def __init__(self, dims):
+        lib = _lib.load()
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        arr = (_lib.GppDims * len(self.dims))(*[_lib.GppDims(*d) for d in self.dims])
+        handle = C.c_void_p()
+        _lib.check(lib.gpp_plan_create(len(self.dims), arr, C.byref(handle)),
+                   "gpp_plan_create")
+        self._h = handle
+        self.workspace_bytes = int(lib.gpp_plan_workspace(handle))
+
+    def info(self) -> dict:
+        inf = _lib.GppPlanInfo()
+        _lib.check(_lib.load().gpp_plan_get_info(self._h, C.byref(inf)),
+                   "gpp_plan_get_info")
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().gpp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_STATE_KEYS = ("aqsmtemp", "aqsntemp", "I_eps_array", "wtilde_array", "vcoul",
+               "wx_array")
+
+
+def sigma_batched(plan: Plan, states, *, out=None, workspace=None, stream=None):
+    """achtemp, asxtemp (complex128 [nstates, nfreq]) for every state via
+    gpp_sigma_batched.  `states` is a sequence of dicts (or 6-tuples) of
+    CUDA tensors in sigma_fwd's layouts, matching the plan's sizes."""
+    torch = _torch()
+    lib = _lib.load()
+    if len(states) != len(plan.dims):
+        raise ValueError(f"plan has {len(plan.dims)} states, got {len(states)}")
+    ins = (_lib.GppInputs * len(states))()
+    dev = None
+    for k, (st, d) in enumerate(zip(states, plan.dims)):
+        if not isinstance(st, dict):
+            st = dict(zip(_STATE_KEYS, st))
+        dims, one, dv = _prepare(*[st[key] for key in _STATE_KEYS], d[1])
+        if (dims.number_bands, dims.nvband, dims.ncouls, dims.ngpown, dims.nfreq) != d:
+            got = (dims.number_bands, dims.nvband, dims.ncouls, dims.ngpown, dims.nfreq)
+            raise ValueError(f"state {k}: tensors have sizes {got}, plan expects {d}")
+        if dev is not None and dv != dev:
+            raise ValueError("all states must be on one device")
+        dev = dv
+        ins[k] = one
+    nw = plan.dims[0][4]
+    shape = (len(states), nw)
+    if out is None:
+        ach = torch.empty(shape, dtype=torch.complex128, device=dev)
+        asx = torch.empty(shape, dtype=torch.complex128, device=dev)
+    else:
+        ach, asx = out
+        _check_tensor("achtemp", ach, torch.complex128, shape, dev)
+        _check_tensor("asxtemp", asx, torch.complex128, shape, dev)
+    if workspace is None:
+        workspace = torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8,
+                                device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    st = lib.gpp_sigma_batched(plan._h, ins, _ptr(ach), _ptr(asx), _ptr(workspace),
+                               workspace.numel(), C.c_void_p(stream))
+    _lib.check(st, "gpp_sigma_batched")
+    return ach, asx

@@ -39,6 +39,14 @@ class GppInputs(C.Structure):
                 ("vcoul", C.c_void_p), ("wx_array", C.c_void_p)]
 
 
+class GppPlanInfo(C.Structure):
+    _fields_ = [("tuned", C.c_int32), ("from_cache", C.c_int32),
+                ("bands_per_group", C.c_int32), ("schedule_order", C.c_int32),
+                ("workgroups", C.c_int32), ("waves", C.c_int32),
+                ("candidates", C.c_int32), ("schedule", C.c_int32),
+                ("total_tiles", C.c_int64), ("tuned_ms", C.c_double)]
+
+
 # (name, restype, argtypes) of every function include/*.h declares
 _SIGNATURES = [
     ("gpp_sigma_fwd_workspace", C.c_size_t, [C.POINTER(GppDims)]),
@@ -50,6 +58,14 @@ _SIGNATURES = [
      [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p,
       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
       C.c_void_p]),
+    ("gpp_plan_create", C.c_int,
+     [C.c_int32, C.POINTER(GppDims), C.POINTER(C.c_void_p)]),
+    ("gpp_plan_workspace", C.c_size_t, [C.c_void_p]),
+    ("gpp_plan_get_info", C.c_int, [C.c_void_p, C.POINTER(GppPlanInfo)]),
+    ("gpp_sigma_batched", C.c_int,
+     [C.c_void_p, C.POINTER(GppInputs), C.c_void_p, C.c_void_p, C.c_void_p,
+      C.c_size_t, C.c_void_p]),
+    ("gpp_plan_destroy", None, [C.c_void_p]),
     ("gpp_status_string", C.c_char_p, [C.c_int]),
     ("gpp_last_error", C.c_char_p, []),
     ("gpp_version", C.c_int, []),

@@ -17,8 +17,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgpp.so")
-SOURCES = ["gpp_api.hip", "gpp_fwd.hip", "gpp_bwd.hip", "gpp_microbench.hip"]
-HEADERS = ["gpp_device.h", "gpp_internal.h"]
+SOURCES = ["gpp_api.hip", "gpp_fwd.hip", "gpp_bwd.hip", "gpp_batched.hip", "gpp_plan.hip",
+           "gpp_microbench.hip"]
+HEADERS = ["gpp_device.h", "gpp_fwd_tile.h", "gpp_internal.h"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

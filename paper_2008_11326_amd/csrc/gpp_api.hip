@@ -9,7 +9,7 @@
 #include "gpp.h"
 #include "gpp_internal.h"
 
-namespace {
+namespace gpp {
 
 thread_local char g_last_error[512] = "";
 
@@ -91,7 +91,15 @@ gpp_status check_inputs(const gpp::Dims32 &d, const gpp_inputs *in, gpp::DevInpu
     return GPP_OK;
 }
 
-}  // namespace
+}  // namespace gpp
+
+using gpp::check_array;
+using gpp::check_dims;
+using gpp::check_inputs;
+using gpp::fail;
+using gpp::g_last_error;
+using gpp::hip_fail;
+using gpp::misaligned;
 
 extern "C" {
 

@@ -1,0 +1,327 @@
+// gpp_batched.hip -- persistent forward over many quasiparticle states of
+// uneven sizes in one launch (gfx950, fp64).
+//
+// The tiles of all states (each state's forward tiles: one G' column x 64
+// G rows, G'-column fastest) are concatenated in a schedule order chosen by
+// the plan.  Persistent wave w takes global tiles w, w + W, w + 2W, ...
+// (W = resident waves), so at any moment the running waves sit on
+// neighbouring tiles of one state -- the same aqsntemp rows and L2
+// locality as the plain forward -- and every wave's cost stays within one
+// tile of the mean (or, in the XCD-chunked schedule, each XCD takes one
+// contiguous, equally costly chunk of the list and its waves round-robin
+// inside it).  Each wave keeps running sums for the state it is in and
+// writes exactly one partial row per state (zeros for states it never
+// touches) into slot [state][wave]; a second kernel adds each state's W rows
+// in a fixed order.  Waves never wait on each other, so the grid needs no
+// co-residency and every wave reaches its exit.  The per-tile arithmetic is
+// the plain forward's (gpp_fwd_tile.h).
+#include "gpp_device.h"
+#include "gpp_fwd_tile.h"
+#include "gpp_internal.h"
+
+namespace gpp {
+
+constexpr int kBatWaves = 4;
+constexpr int kBatThreads = kBatWaves * kWave;
+
+// Write the wave's running sums for state s (wave-uniform values) and
+// clear them.
+template <int NW>
+__device__ __forceinline__ void flush_state(const StateDesc *__restrict__ st, int s, int wave,
+                                            int nwaves, int lane, cplx (&ach)[NW],
+                                            cplx (&asx)[NW], double *__restrict__ partials)
+{
+    if (lane == 0) {
+        double *dst = partials + ((size_t)st[s].out_index * nwaves + wave) * (4 * NW);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            dst[4 * w + 0] = ach[w].re;
+            dst[4 * w + 1] = ach[w].im;
+            dst[4 * w + 2] = asx[w].re;
+            dst[4 * w + 3] = asx[w].im;
+        }
+    }
+#pragma unroll
+    for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
+}
+
+// Up to three frequencies the kernel is held to 128 VGPRs (4 waves per
+// SIMD); more frequencies need the larger register file per wave.
+template <int NW, int BU>
+__global__ void __launch_bounds__(kBatThreads)
+__attribute__((amdgpu_waves_per_eu(NW <= 3 ? 4 : 1)))
+batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_tiles, int nwaves,
+                   double *__restrict__ partials, const long *__restrict__ xcd_chunks)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int wave = (int)xcd_remap(blockIdx.x, gridDim.x) * kBatWaves + wid;
+    if (wave >= nwaves) return;  // wave-uniform; no barriers in this kernel
+
+    // Tile sequence of this wave: t0, t0 + step, ... below t_end.  Global
+    // round-robin, or (xcd_chunks != NULL) round-robin among the waves of
+    // this wave's XCD over that XCD's contiguous chunk of the tile list, so
+    // one XCD's L2 serves each g-tile as in the plain forward.
+    long t0 = wave, step = nwaves, t_end = total_tiles;
+    if (xcd_chunks) {
+        const uint32_t kXcd = 8, x = blockIdx.x % kXcd, i = blockIdx.x / kXcd;
+        const uint32_t per = gridDim.x / kXcd, rem = gridDim.x % kXcd;
+        const long waves_x = (long)(per + (x < rem ? 1 : 0)) * kBatWaves;
+        t0 = xcd_chunks[x] + (long)i * kBatWaves + wid;
+        step = waves_x;
+        t_end = xcd_chunks[x + 1];
+    }
+
+    // running sums of the current state, kept wave-uniform (scalar
+    // registers): each tile's contribution is summed over the wave as soon
+    // as the tile is done, so no vector registers live across tiles
+    cplx ach[NW], asx[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
+
+    int s = 0;  // schedule position of the state holding tile t
+    for (long t = t0; t < t_end; t += step) {
+        while (t >= st[s + 1].tile_begin) {  // st[nstates].tile_begin == total_tiles
+            flush_state<NW>(st, s, wave, nwaves, lane, ach, asx, partials);
+            ++s;
+        }
+        const StateDesc d = st[s];
+        const long local = t - d.tile_begin;
+        const int gt = (int)(local / d.np);
+        const int p = (int)(local - (long)gt * d.np);
+        cplx a[NW], x[NW];
+        fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, p, gt, lane, as_global(d.aqsm),
+                              as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
+                              as_global(d.vcoul), as_global(d.wx), a, x);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            ach[w].re = to_uniform(ach[w].re + wave_sum(a[w].re));
+            ach[w].im = to_uniform(ach[w].im + wave_sum(a[w].im));
+            asx[w].re = to_uniform(asx[w].re + x[w].re);  // x: already wave totals
+            asx[w].im = to_uniform(asx[w].im + x[w].im);
+        }
+    }
+    for (; s < nstates; ++s) flush_state<NW>(st, s, wave, nwaves, lane, ach, asx, partials);
+}
+
+// Work-queue form: waves take chunks of chunk_tiles consecutive tiles (never
+// crossing a state) from a global counter in increasing order, so the
+// chunks in flight stay a contiguous window of the tile list and faster
+// CUs take more chunks.  Each chunk writes its own partial row, which makes
+// the result independent of which wave ran which chunk.
+// With queue_begin != NULL there are kXcdCount queues: queue x hands out
+// chunks [queue_begin[x], queue_begin[x+1]) (an equal-cost contiguous region
+// of the chunk list) through counter[x]; waves start on their own XCD's
+// queue (workgroups reach XCDs round-robin), keeping one XCD's L2 on one
+// region, and move on to the other queues once theirs is empty.  Each queue
+// is left for good when it runs dry, so a wave makes at most kXcdCount
+// failed takes and every wave reaches the exit.
+template <int NW, int BU>
+__global__ void __launch_bounds__(kBatThreads)
+__attribute__((amdgpu_waves_per_eu(NW <= 3 ? 4 : 1)))
+batched_queue(const StateDesc *__restrict__ st, long nchunks, int chunk_tiles,
+              unsigned long long *__restrict__ counter, const long *__restrict__ queue_begin,
+              double *__restrict__ partials)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nq = queue_begin ? kXcdCount : 1;
+    const int q0 = queue_begin ? (int)(blockIdx.x % kXcdCount) : 0;
+    int qi = 0;  // queues tried so far
+    int s = 0;   // schedule position of the state holding chunk c
+    for (;;) {
+        const int q = (q0 + qi) % nq;
+        const long qlo = queue_begin ? queue_begin[q] : 0;
+        const long qhi = queue_begin ? queue_begin[q + 1] : nchunks;
+        unsigned long long c0 = 0;
+        if (lane == 0) c0 = atomicAdd(counter + q, 1ull);
+        const long k = (long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                   (int)(c0 >> 32)) << 32) |
+                              (unsigned)__builtin_amdgcn_readfirstlane((int)c0));
+        const long c = qlo + k;
+        if (c >= qhi) {  // this queue is dry (wave-uniform)
+            if (++qi >= nq) break;
+            continue;
+        }
+        if (c < st[s].chunk_begin) s = 0;  // moved back to an earlier region
+        while (c >= st[s + 1].chunk_begin) ++s;
+        const StateDesc d = st[s];
+        const long t0 = d.tile_begin + (c - d.chunk_begin) * chunk_tiles;
+        const long tmax = st[s + 1].tile_begin;
+        const long t1 = t0 + chunk_tiles < tmax ? t0 + chunk_tiles : tmax;
+        cplx ach[NW], asx[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
+        for (long t = t0; t < t1; ++t) {
+            const long local = t - d.tile_begin;
+            const int gt = (int)(local / d.np);
+            const int p = (int)(local - (long)gt * d.np);
+            cplx a[NW], x[NW];
+            fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, p, gt, lane, as_global(d.aqsm),
+                                  as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
+                                  as_global(d.vcoul), as_global(d.wx), a, x);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                ach[w].re = to_uniform(ach[w].re + wave_sum(a[w].re));
+                ach[w].im = to_uniform(ach[w].im + wave_sum(a[w].im));
+                asx[w].re = to_uniform(asx[w].re + x[w].re);
+                asx[w].im = to_uniform(asx[w].im + x[w].im);
+            }
+        }
+        if (lane == 0) {
+            double *dst = partials + (size_t)c * (4 * NW);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                dst[4 * w + 0] = ach[w].re;
+                dst[4 * w + 1] = ach[w].im;
+                dst[4 * w + 2] = asx[w].re;
+                dst[4 * w + 3] = asx[w].im;
+            }
+        }
+    }
+}
+
+__global__ void zero_counters(unsigned long long *counter, int n)
+{
+    if ((int)threadIdx.x < n) counter[threadIdx.x] = 0ull;
+}
+
+// Per state (one workgroup per schedule position k): the sum of its chunk
+// rows [chunk_begin[k], chunk_begin[k+1]) in a fixed order.
+template <int NW>
+__global__ void __launch_bounds__(256)
+batched_reduce_chunks(const StateDesc *__restrict__ st, const double *__restrict__ partials,
+                      double2 *__restrict__ ach, double2 *__restrict__ asx)
+{
+    constexpr int R = 4 * NW;
+    __shared__ double red[4][R];
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const long c0 = st[k].chunk_begin, c1 = st[k + 1].chunk_begin;
+    const int s = st[k].out_index;
+    double acc[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] = 0.0;
+    for (long c = c0 + threadIdx.x; c < c1; c += 256) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[j] += partials[(size_t)c * R + j];
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == 0) red[wid][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                         red[3][threadIdx.x];
+        const int w = threadIdx.x / 4, c = threadIdx.x % 4;
+        double *dst = reinterpret_cast<double *>(c < 2 ? ach + (size_t)s * NW + w
+                                                       : asx + (size_t)s * NW + w);
+        dst[c & 1] = v;
+    }
+}
+
+// achtemp[s][w], asxtemp[s][w] = sum over the W partial rows of state s, in
+// a fixed order (thread t adds rows t, t+256, ..., then a fixed tree).
+template <int NW>
+__global__ void __launch_bounds__(256)
+batched_reduce(const double *__restrict__ partials, int nwaves, double2 *__restrict__ ach,
+               double2 *__restrict__ asx)
+{
+    constexpr int R = 4 * NW;
+    __shared__ double red[4][R];
+    const int s = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    double acc[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] = 0.0;
+    const double *base = partials + (size_t)s * nwaves * R;
+    for (int i = threadIdx.x; i < nwaves; i += 256) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[j] += base[(size_t)i * R + j];
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == 0) red[wid][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                         red[3][threadIdx.x];
+        const int w = threadIdx.x / 4, c = threadIdx.x % 4;
+        double *dst = reinterpret_cast<double *>(c < 2 ? ach + (size_t)s * NW + w
+                                                       : asx + (size_t)s * NW + w);
+        dst[c & 1] = v;
+    }
+}
+
+template <int NW, int BU>
+static const void *persistent_ptr(int sched)
+{
+    return (sched == kSchedQueue || sched == kSchedXcdQueues)
+               ? reinterpret_cast<const void *>(&batched_queue<NW, BU>)
+               : reinterpret_cast<const void *>(&batched_persistent<NW, BU>);
+}
+
+const void *batched_kernel(int nw, int bu, int sched)
+{
+#define GPP_K(NWV)                                                     \
+    case NWV:                                                          \
+        if (bu == 1) return persistent_ptr<NWV, 1>(sched);             \
+        if (bu == 2 && NWV <= 4) return persistent_ptr<NWV, 2>(sched); \
+        if (bu == 3 && NWV <= 3) return persistent_ptr<NWV, 3>(sched); \
+        return nullptr;
+    switch (nw) {
+        GPP_K(1) GPP_K(2) GPP_K(3) GPP_K(4) GPP_K(5) GPP_K(6) GPP_K(7) GPP_K(8)
+    }
+#undef GPP_K
+    return nullptr;
+}
+
+template <int NW>
+static void launch_reduce(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st)
+{
+    if (L.sched == kSchedQueue || L.sched == kSchedXcdQueues)
+        hipLaunchKernelGGL(batched_reduce_chunks<NW>, dim3(L.nstates), dim3(256), 0, st, L.desc,
+                           L.partials, ach, asx);
+    else
+        hipLaunchKernelGGL(batched_reduce<NW>, dim3(L.nstates), dim3(256), 0, st, L.partials,
+                           L.blocks * kBatWaves, ach, asx);
+}
+
+hipError_t launch_batched(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st)
+{
+    const void *k = batched_kernel(L.nw, L.bu, L.sched);
+    if (!k) return hipErrorInvalidValue;
+    hipError_t e;
+    if (L.sched == kSchedQueue || L.sched == kSchedXcdQueues) {
+        hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, st, L.counter, kXcdCount);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const long *qb = L.sched == kSchedXcdQueues ? L.queue_begin : nullptr;
+        void *args[] = {(void *)&L.desc,    (void *)&L.nchunks, (void *)&L.chunk_tiles,
+                        (void *)&L.counter, (void *)&qb,        (void *)&L.partials};
+        e = hipLaunchKernel(k, dim3(L.blocks), dim3(kBatThreads), args, 0, st);
+    } else {
+        const int nwaves = L.blocks * kBatWaves;
+        const long *chunks = L.sched == kSchedXcdChunks ? L.xcd_chunks : nullptr;
+        void *args[] = {(void *)&L.desc,     (void *)&L.nstates,  (void *)&L.total_tiles,
+                        (void *)&nwaves,     (void *)&L.partials, (void *)&chunks};
+        e = hipLaunchKernel(k, dim3(L.blocks), dim3(kBatThreads), args, 0, st);
+    }
+    if (e != hipSuccess) return e;
+    switch (L.nw) {
+    case 1: launch_reduce<1>(L, ach, asx, st); break;
+    case 2: launch_reduce<2>(L, ach, asx, st); break;
+    case 3: launch_reduce<3>(L, ach, asx, st); break;
+    case 4: launch_reduce<4>(L, ach, asx, st); break;
+    case 5: launch_reduce<5>(L, ach, asx, st); break;
+    case 6: launch_reduce<6>(L, ach, asx, st); break;
+    case 7: launch_reduce<7>(L, ach, asx, st); break;
+    case 8: launch_reduce<8>(L, ach, asx, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gpp

@@ -205,7 +205,7 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
                     Z = cadd(Z, KS);
                     W = cadd(W, LS);
                 }
-                const cplx an = load_row_elem(aqsn + (size_t)nn * ng, ng, goff);
+                const cplx an = load_row_elem(as_global(aqsn) + (size_t)nn * ng, ng, goff);
                 const cplx am = cload(am_col + (size_t)nn * ng);
                 const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
                 cmac(Ge, cM, Z);

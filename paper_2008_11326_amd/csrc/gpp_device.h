@@ -29,10 +29,24 @@ struct cplx {
     double re, im;
 };
 
+// Global-memory pointer types: pointers read from memory (not kernel
+// arguments) keep their address space this way, so loads through them
+// compile to global or scalar loads rather than flat ones.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)p;
+}
+
 __device__ __forceinline__ cplx cmake(double re, double im) { return {re, im}; }
 __device__ __forceinline__ cplx cload(const double2 *p) {
     double2 v = *p;
     return {v.x, v.y};
+}
+__device__ __forceinline__ cplx cload(gptr<double2> p) {
+    return {p->x, p->y};  // member reads: one 16-byte load after vectorising
 }
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) {
@@ -143,20 +157,25 @@ __device__ __forceinline__ double wave_sum(double v) {
 // base is wave-uniform: a raw buffer load with the row in a scalar buffer
 // descriptor (gfx9 descriptor word 3 = 0x00020000) and the offset in a
 // vector register.  Offsets at or beyond the row length read as zero.
-__device__ __forceinline__ cplx load_row_elem(const double2 *row, int len, uint32_t off) {
+__device__ __forceinline__ cplx load_row_elem(gptr<double2> row, int len, uint32_t off) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<double2 *>(row), (short)0, len * (int)sizeof(double2), 0x00020000);
+        (void *)(const double2 *)row, (short)0, len * (int)sizeof(double2), 0x00020000);
     const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
     return {v.x, v.y};
 }
 
-// Wave total of v, returned as a wave-uniform (scalar-register) value.
-__device__ __forceinline__ double wave_sum_uniform(double v) {
-    const double t = wave_sum(v);
+// Mark a pointer read from memory as a global-memory pointer, so accesses
+// through it compile to global/scalar loads instead of flat ones (pointers
+// passed as kernel arguments get this from address-space inference).
+// A wave-uniform value moved into scalar registers (the value of lane 0).
+__device__ __forceinline__ double to_uniform(double t) {
     const int lo = __builtin_amdgcn_readfirstlane(__double2loint(t));
     const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(t));
     return __hiloint2double(hi, lo);
 }
+
+// Wave total of v, returned as a wave-uniform (scalar-register) value.
+__device__ __forceinline__ double wave_sum_uniform(double v) { return to_uniform(wave_sum(v)); }
 
 // Map a hardware workgroup id to a logical one so that each of the 8 XCDs
 // (which receive workgroups round-robin) walks a contiguous logical range

@@ -1,0 +1,147 @@
+// gpp_fwd_tile.h -- the forward work of one wave tile (one G' column p x
+// 64 consecutive G rows), shared by the plain forward and the persistent
+// batched kernel so both run the same arithmetic.  See gpp_fwd.hip for
+// the derivation.
+#pragma once
+
+#include "gpp_device.h"
+
+namespace gpp {
+
+// CH-only accumulation for BU consecutive unoccupied bands starting at n.
+// aqsntemp[n][g] is read through a buffer descriptor for the row (scalar
+// registers) plus the lane's 32-bit byte offset, so the per-band address
+// arithmetic stays on the scalar unit.
+template <int NW, int BU>
+__device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aqsn,
+                                         uint32_t goff, gptr<double2> am_col,
+                                         gptr<double> wx, double a, double wi2, double thr,
+                                         cplx (&P1)[NW], cplx (&P2)[NW])
+{
+    constexpr int K = BU * NW;
+    cplx qm[BU];
+    double xs[K], dc[K], r[K];
+    bool isA[K];
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+        const cplx an = load_row_elem(aqsn + (size_t)(n + u) * ng, ng, goff);
+        const cplx am = cload(am_col + (size_t)(n + u) * ng);
+        qm[u] = cmul_conj(an, am);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double dr = xs[k] - a;
+        const double wd = fma(dr, dr, wi2);
+        isA[k] = wd > thr;
+        dc[k] = fmax(wd, kLimitTwo);
+    }
+    batch_reciprocal<K>(dc, r);
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int k = u * NW + w;
+            const double re = mask_keep(isA[k], r[k]);
+            const double rx = re * xs[k];
+            P1[w].re = fma(rx, qm[u].re, P1[w].re);
+            P1[w].im = fma(rx, qm[u].im, P1[w].im);
+            P2[w].re = fma(re, qm[u].re, P2[w].re);
+            P2[w].im = fma(re, qm[u].im, P2[w].im);
+        }
+    }
+}
+
+// One tile: lane g = gt*64 + lane of column p.  On return ach[w] holds this
+// lane's Coulomb-hole contribution (still to be summed over the wave) and
+// asx[w] the wave's screened-exchange total (wave-uniform).  Must be called
+// by all 64 lanes of a wave together (wave reductions inside).
+template <int NW, int BU>
+__device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int gt, int lane,
+                                              gptr<double2> aqsm, gptr<double2> aqsn,
+                                              gptr<double2> ieps, gptr<double2> wt,
+                                              gptr<double> vcoul, gptr<double> wx,
+                                              cplx (&ach)[NW], cplx (&asx)[NW])
+{
+    const int g = gt * kWave + lane;
+    const bool valid = g < ng;
+    const int gc = valid ? g : ng - 1;  // clamped, contribution zeroed
+
+    const cplx om = cload(wt + (size_t)p * ng + gc);
+    const double a = om.re, b = om.im;
+    const double wi2 = b * b;
+    const double wtr = fma(a, a, wi2);
+    const double thr = branch_a_threshold(wtr);
+
+    cplx P1[NW], P2[NW], SX[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) P1[w] = P2[w] = SX[w] = cmake(0.0, 0.0);
+
+    const gptr<double2> an_col = aqsn + gc;
+    const gptr<double2> am_col = aqsm + p;
+    const uint32_t goff = (uint32_t)gc * (uint32_t)sizeof(double2);
+    const cplx e = cload(ieps + (size_t)p * ng + gc);
+    const double v = valid ? vcoul[gc] : 0.0;
+    const cplx ev = cscale(v, e);
+
+    // occupied bands: screened exchange (SX) and Coulomb hole (CH)
+    for (int n = 0; n < nv; ++n) {
+        const cplx an = cload(an_col + (size_t)n * ng);
+        const cplx am = cload(am_col + (size_t)n * ng);
+        const cplx qm = cmul_conj(an, am);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const double x = wx[(size_t)w * nb + n];
+            const double dr = x - a;
+            const double wd = fma(dr, dr, wi2);
+            const bool isA = wd > thr;
+            const double r = isA ? rcp_nr2(wd) : 0.0;
+            const double rx = r * x;
+            P1[w].re = fma(rx, qm.re, P1[w].re);
+            P1[w].im = fma(rx, qm.im, P1[w].im);
+            P2[w].re = fma(r, qm.re, P2[w].re);
+            P2[w].im = fma(r, qm.im, P2[w].im);
+            // ssx / e
+            const cplx d = cmake(dr, -b);    // x - om
+            const cplx s = cmake(x + a, b);  // x + om
+            cplx t = cmake(0.0, 0.0);
+            if (isA) {
+                t = cdiv(cmul(om, om), cmul(d, s));
+            } else if (branch_b_holds(wtr, wd)) {
+                t = cdiv(om, cmake(-2.0 * s.re, -2.0 * s.im));
+            }
+            cmac(SX[w], qm, t);
+        }
+    }
+    // The exchange sums are finished here and reduced over the wave into
+    // scalar registers, so they hold no vector registers in the hot loop.
+    if (nv > 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const cplx t = cmul(ev, SX[w]);
+            asx[w] = cmake(wave_sum_uniform(t.re), wave_sum_uniform(t.im));
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) asx[w] = cmake(0.0, 0.0);
+    }
+
+    // unoccupied bands: CH only -- the hot loop
+    int n = nv;
+    for (; n + BU <= nb; n += BU)
+        ch_group<NW, BU>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, P1, P2);
+    for (; n < nb; ++n)
+        ch_group<NW, 1>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, P1, P2);
+
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        // S = om P1 - wtr P2
+        cplx S = cmul(om, P1[w]);
+        S.re = fma(-wtr, P2[w].re, S.re);
+        S.im = fma(-wtr, P2[w].im, S.im);
+        ach[w] = cscale(0.5, cmul(ev, S));
+    }
+}
+
+}  // namespace gpp

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "gpp.h"
+
 namespace gpp {
 
 // Validated loop bounds (every value < 2^31).
@@ -38,6 +40,52 @@ struct BwdGeometry {
 struct BwdOutputs {
     double2 *grad_am, *grad_an, *grad_ieps, *grad_wt;  // NULL = not wanted
 };
+
+// One state of a batched call, in schedule order (device-side table with
+// one extra sentinel entry whose tile_begin is the total tile count).
+struct StateDesc {
+    const double2 *aqsm, *aqsn, *ieps, *wt;
+    const double *vcoul, *wx;
+    int nb, nv, ng, np;
+    long tile_begin;   // first global tile of this state
+    long chunk_begin;  // first work-queue chunk of this state
+    int out_index;     // position in the caller's state order
+    int pad;
+};
+
+// How the persistent waves walk the concatenated tile list.
+enum BatchedSchedule {
+    kSchedRoundRobin = 0,  // wave w: tiles w, w + W, ...
+    kSchedXcdChunks = 1,   // one equal-cost contiguous chunk per XCD
+    kSchedQueue = 2,       // waves take chunk_tiles-tile chunks from a counter
+    kSchedXcdQueues = 3,   // one such queue per XCD over its own region, with stealing
+};
+
+struct BatchedLaunch {
+    int nw, bu, blocks, sched;
+    const StateDesc *desc;
+    int nstates;
+    long total_tiles;
+    const long *xcd_chunks;  // kSchedXcdChunks: kXcdCount + 1 boundaries
+    long nchunks;            // kSchedQueue
+    int chunk_tiles;         // kSchedQueue
+    unsigned long long *counter;  // queue schedules: kXcdCount counters, zeroed by the launch
+    const long *queue_begin;      // kSchedXcdQueues: kXcdCount + 1 chunk boundaries
+    double *partials;
+};
+
+const void *batched_kernel(int nw, int bu, int sched);
+hipError_t launch_batched(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st);
+constexpr int kXcdCount = 8;
+
+// host-side validation and error reporting shared by the entry points
+extern thread_local char g_last_error[512];
+gpp_status fail(gpp_status s, const char *fmt, ...);
+gpp_status hip_fail(hipError_t e, const char *where);
+gpp_status check_dims(const gpp_dims *d, Dims32 *out);
+gpp_status check_array(const char *name, const void *p, int64_t elems, size_t align);
+gpp_status check_inputs(const Dims32 &d, const gpp_inputs *in, DevInputs *out);
+bool misaligned(const void *p, size_t a);
 
 FwdGeometry fwd_geometry(const Dims32 &d);
 BwdGeometry bwd_geometry(const Dims32 &d);

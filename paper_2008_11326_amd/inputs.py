@@ -44,8 +44,8 @@ import numpy as np
 
 __all__ = [
     "Dims", "Problem", "Workload", "WORKLOADS", "make_problem",
-    "make_upstream_grad", "make_fd_entries", "batched_dims", "make_batched",
-    "workload",
+    "make_problem_device", "make_upstream_grad", "make_fd_entries",
+    "batched_dims", "make_batched", "workload",
 ]
 
 
@@ -200,3 +200,32 @@ def make_batched(seed: int = BATCHED_SEED, nstates: int = BATCHED_STATES,
     idx = range(nstates) if states is None else states
     for s in idx:
         yield s, make_problem(dims[s], [seed, s])
+
+
+def make_problem_device(dims: Dims, seed: int, device="cuda:0") -> dict:
+    """The same value distributions as make_problem, drawn directly on the
+    device with torch's generator (for throughput runs whose size makes
+    host-side generation the bottleneck; not bit-identical to
+    make_problem, so never used where an oracle value is compared)."""
+    import torch
+    nb, nv, ng, npw, nw = dims.as_tuple()
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    f64 = torch.float64
+
+    def uni(shape, lo, hi):
+        return torch.rand(shape, generator=gen, dtype=f64, device=device) * (hi - lo) + lo
+
+    e_n = uni((nb,), -1.0, 1.0)
+    e_lk = uni((1,), -1.0, 1.0)
+    cu = lambda shape, lr, hr, li, hi: torch.complex(uni(shape, lr, hr), uni(shape, li, hi))
+    out = {
+        "aqsmtemp": cu((nb, ng), -0.5, 0.5, -0.5, 0.5),
+        "aqsntemp": cu((nb, ng), -0.5, 0.5, -0.5, 0.5),
+        "I_eps_array": cu((npw, ng), -0.5, 0.5, -0.5, 0.5),
+        "wtilde_array": cu((npw, ng), 0.5, 2.0, -0.05, 0.05),
+        "vcoul": uni((ng,), 0.1, 1.0),
+    }
+    shift = (torch.arange(nw, dtype=f64, device=device) - (nw - 1) / 2.0) * 0.5
+    out["wx_array"] = ((e_lk - e_n)[None, :] + shift[:, None]).contiguous()
+    return out

@@ -158,3 +158,21 @@ def test_bwd_workspace_grows_with_rows_bands_columns(lib):
     c = lib.gpp_sigma_bwd_workspace(C.byref(_dims(nb=16, ng=512, npw=10)))
     assert 0 < a < b < c
     assert lib.gpp_sigma_bwd_workspace(None) == 0
+
+
+def test_plan_validation_before_any_device_call(lib):
+    handle = C.c_void_p(123)
+    bad = (_lib.GppDims * 2)(_lib.GppDims(8, 2, 100, 10, 3), _lib.GppDims(8, 9, 100, 10, 3))
+    assert lib.gpp_plan_create(2, bad, C.byref(handle)) == 1
+    assert "state 1" in lib.gpp_last_error().decode() and handle.value is None
+    mixed = (_lib.GppDims * 2)(_lib.GppDims(8, 2, 100, 10, 3), _lib.GppDims(8, 2, 100, 10, 2))
+    assert lib.gpp_plan_create(2, mixed, C.byref(handle)) == 1
+    assert "nfreq" in lib.gpp_last_error().decode()
+    assert lib.gpp_plan_create(0, bad, C.byref(handle)) == 1
+    assert lib.gpp_plan_create(1, None, C.byref(handle)) == 1
+    assert lib.gpp_plan_create(1, bad, None) == 1
+    assert lib.gpp_sigma_batched(None, None, None, None, None, 0, None) == 1
+    assert lib.gpp_plan_workspace(None) == 0
+    info = _lib.GppPlanInfo()
+    assert lib.gpp_plan_get_info(None, C.byref(info)) == 1
+    lib.gpp_plan_destroy(None)  # no-op

@@ -1,0 +1,177 @@
+"""GPU parity of the persistent batched forward (gpp_sigma_batched) against
+the oracle and the plain forward, its graph replays, and its autotuner
+cache.  Every state's achtemp/asxtemp must match at 1e-12 relative."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11326_amd import inputs as I
+from tests.gpu_helpers import assert_parity, load_golden, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+UNEVEN = [I.Dims(9, 2, 300, 15, 3), I.Dims(33, 2, 777, 38, 3), I.Dims(4, 0, 64, 3, 3),
+          I.Dims(6, 6, 129, 7, 3), I.Dims(5, 1, 70, 0, 3), I.Dims(1, 1, 1, 1, 3),
+          I.Dims(64, 2, 2048, 102, 3), I.Dims(17, 3, 500, 25, 3)]
+
+
+@pytest.fixture(scope="module")
+def gpp():
+    import paper_2008_11326_amd as gpp
+    from paper_2008_11326_amd import _lib
+    _lib.load()
+    return gpp
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    probs = [I.make_problem(d, [17, k], 0.05 if k % 2 else 0.0) for k, d in enumerate(UNEVEN)]
+    refs = [oracle.sigma_fwd(p) for p in probs]
+    return probs, refs, [to_device(p) for p in probs]
+
+
+def test_uneven_states_vs_oracle_and_plain(gpp, uneven, tmp_path, monkeypatch):
+    import torch
+    monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    probs, refs, dev = uneven
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    ach, asx = gpp.sigma_batched(plan, dev)
+    torch.cuda.synchronize()
+    info = plan.info()
+    say(f"[batched] plan {info}")
+    assert info["tuned"] == 1 and info["candidates"] >= 2
+    for k, (p, ref, d) in enumerate(zip(probs, refs, dev)):
+        assert_parity(ach[k].cpu().numpy(), ref[0], ref[2], f"state {k} achtemp")
+        assert_parity(asx[k].cpu().numpy(), ref[1], ref[3], f"state {k} asxtemp")
+        pa, px = gpp.sigma_fwd(**d, nvband=p.dims.nvband)
+        g = pa.cpu().numpy(), px.cpu().numpy()
+        for got, plain in ((ach[k].cpu().numpy(), g[0]), (asx[k].cpu().numpy(), g[1])):
+            scale = np.abs(plain) + 1e-300
+            assert np.all(np.abs(got - plain) <= 1e-12 * scale + 1e-300)
+    plan.close()
+
+
+def test_graph_replays_are_bitwise_identical(gpp, uneven, tmp_path, monkeypatch):
+    import torch
+    monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    probs, _, dev = uneven
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    nw = probs[0].dims.nfreq
+    out = (torch.empty((len(probs), nw), dtype=torch.complex128, device="cuda:0"),
+           torch.empty((len(probs), nw), dtype=torch.complex128, device="cuda:0"))
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda:0")
+    gpp.sigma_batched(plan, dev, out=out, workspace=ws)  # tunes, captures
+    torch.cuda.synchronize()
+    first = [o.cpu().numpy().copy() for o in out]
+    for rep in range(4):
+        # unrelated eager work and synchronisation between replays
+        junk = torch.randn(1 << 20, device="cuda:0", dtype=torch.float64)
+        junk.sum().item()
+        out[0].zero_()
+        out[1].zero_()
+        gpp.sigma_batched(plan, dev, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        for a, b in zip(first, out):
+            assert np.array_equal(a, b.cpu().numpy()), f"replay {rep} differs"
+    plan.close()
+
+
+def test_new_input_pointers_and_outputs(gpp, uneven, tmp_path, monkeypatch):
+    """Alternate two input sets (descriptor re-upload, same graph) and move
+    the outputs (re-capture); every call matches its own oracle values."""
+    import torch
+    monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    probs, refs, dev_a = uneven
+    probs_b = [I.make_problem(p.dims, [23, k]) for k, p in enumerate(probs)]
+    refs_b = [oracle.sigma_fwd(p) for p in probs_b]
+    dev_b = [to_device(p) for p in probs_b]
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    for it, (dv, rf) in enumerate([(dev_a, refs), (dev_b, refs_b), (dev_a, refs),
+                                   (dev_b, refs_b)]):
+        ach, asx = gpp.sigma_batched(plan, dv)  # fresh outputs each call
+        torch.cuda.synchronize()
+        for k, ref in enumerate(rf):
+            assert_parity(ach[k].cpu().numpy(), ref[0], ref[2], f"call {it} state {k}")
+            assert_parity(asx[k].cpu().numpy(), ref[1], ref[3], f"call {it} state {k}")
+    plan.close()
+
+
+TUNE_SCRIPT = r"""
+import json, sys, os
+sys.path.insert(0, {root!r})
+import numpy as np, torch
+import paper_2008_11326_amd as gpp
+from paper_2008_11326_amd import inputs as I
+dims = [I.Dims(8, 2, 256, 12, 3), I.Dims(20, 2, 640, 30, 3)]
+states = []
+for k, d in enumerate(dims):
+    p = I.make_problem(d, [5, k])
+    states.append([torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0") for a in p.arrays()])
+plan = gpp.Plan([d.as_tuple() for d in dims])
+ach, asx = gpp.sigma_batched(plan, states)
+torch.cuda.synchronize()
+print(json.dumps(plan.info()))
+"""
+
+
+def _tune_proc(cache, env_extra=None):
+    env = dict(os.environ, GPP_TUNE_CACHE=str(cache))
+    env.update(env_extra or {})
+    r = subprocess.run([sys.executable, "-c", TUNE_SCRIPT.format(root=ROOT)], env=env,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_tuning_cache_roundtrip_and_corruption(tmp_path):
+    cache = tmp_path / "tune.json"
+    first = _tune_proc(cache)
+    assert first["tuned"] == 1 and first["from_cache"] == 0 and first["tuned_ms"] > 0
+    saved = json.loads(cache.read_text())
+    assert len(saved) == 1
+    second = _tune_proc(cache)
+    assert second["from_cache"] == 1
+    assert (second["bands_per_group"], second["schedule_order"]) == \
+        (first["bands_per_group"], first["schedule_order"])
+    cache.write_text("{ this is not json ]")
+    third = _tune_proc(cache)
+    assert third["from_cache"] == 0 and third["tuned"] == 1
+    assert json.loads(cache.read_text())  # rewritten as valid JSON
+    off = _tune_proc(tmp_path / "other.json", {"GPP_AUTOTUNE": "off"})
+    assert off["tuned"] == 1 and off["tuned_ms"] == 0
+    assert not (tmp_path / "other.json").exists()
+
+
+def test_batched_workload_subset_against_golden(gpp, tmp_path, monkeypatch):
+    """States of the 64-state batched workload at full size (the smallest,
+    the largest and a spread between) against oracle outputs written by
+    tests/golden/make_golden.py."""
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "fwd_batched.json")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/fwd_batched.json not generated")
+    gold = json.load(open(path))["states"]
+    dims = I.batched_dims()
+    size = lambda s: dims[s].ch_terms
+    have = sorted(int(s) for s in gold)
+    pick = sorted({min(have, key=size), max(have, key=size)} |
+                  set(have[:: max(1, len(have) // 5)]))[:7]
+    monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    say(f"[batched] golden subset states {pick}")
+    probs = dict(I.make_batched(states=pick))
+    plan = gpp.Plan([dims[s].as_tuple() for s in pick])
+    ach, asx = gpp.sigma_batched(plan, [to_device(probs[s]) for s in pick])
+    torch.cuda.synchronize()
+    c = lambda pairs: np.array([complex(a, b) for a, b in pairs])
+    for k, s in enumerate(pick):
+        g = gold[str(s)]
+        assert_parity(ach[k].cpu().numpy(), c(g["achtemp"]), g["ach_abs_sum"], f"state {s}")
+        assert_parity(asx[k].cpu().numpy(), c(g["asxtemp"]), g["asx_abs_sum"], f"state {s}")
+    plan.close()

@@ -20,10 +20,13 @@
 //
 // Kernels: bwd_pairs (lane = g, wave-uniform p, bands serial) writes
 // dwtilde and dI_eps and, per workgroup of 256 rows, partial sums of
-// daqsmtemp; bwd_bands (lane = g, a wave owns kBandTile bands and walks
-// every p) writes daqsntemp; reduce_am sums the daqsmtemp partials in a
-// fixed order and zero-fills columns >= ngpown.  No atomics: results are
-// bitwise reproducible.
+// daqsmtemp.  The per-lane daqsmtemp terms of kSlab bands are parked in a
+// per-wave LDS slab and summed together (8 lanes per band, then a DPP sum
+// over the 8), instead of one 64-lane shuffle reduction per band.
+// bwd_bands (lane = g, a wave owns kBandTile bands and walks every p)
+// writes daqsntemp; reduce_am sums the daqsmtemp partials in a fixed order
+// and zero-fills columns >= ngpown.  No atomics: results are bitwise
+// reproducible.
 #include "gpp_device.h"
 #include "gpp_internal.h"
 
@@ -33,8 +36,14 @@ constexpr int kBwdWaves = 4;
 constexpr int kBwdThreads = kBwdWaves * kWave;
 constexpr int kRowsPerBlock = kBwdWaves * kWave;  // g rows per pairs workgroup
 constexpr int kBwdGroup = 3;                       // bands per batch-inverted group
-constexpr int kChunk = 48;                         // bands per LDS flush (multiple of 3)
-constexpr int kBandTile = 6;                       // bands per bands-kernel wave
+constexpr int kChunk = 48;                         // bands per LDS flush (multiple of kSlab)
+constexpr int kSlab = 6;                           // bands per in-wave transpose (two groups)
+constexpr int kOctet = 8;                          // lanes that share one band's row sum
+#ifndef GPP_BWD_BAND_TILE
+#define GPP_BWD_BAND_TILE 3
+#endif
+constexpr int kBandTile = GPP_BWD_BAND_TILE;       // bands per bands-kernel wave
+static_assert(kBandTile % kBwdGroup == 0, "band tile must be whole groups");
 
 // Upstream gradient scaled for the kernels: gh[w] = ga[w]/2 and
 // xgh[w][n] = wx[w][n] ga[w]/2, written once by bwd_prepare.
@@ -49,6 +58,33 @@ __global__ void bwd_prepare(int nb, int nw, const double *__restrict__ wx,
         const double x = wx[i];
         xgh[i] = make_double2(0.5 * x * ga[w].x, 0.5 * x * ga[w].y);
     }
+}
+
+// Lane exchange inside a row of 16 lanes (DPP), both halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each aligned group of 8 lanes; every lane of the group gets it.
+__device__ __forceinline__ double octet_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_f64<0x141>(v);  // row_half_mirror: lane i <-> 7 - i within 8
+    return v;
+}
+
+// Order this wave's LDS writes before its later LDS reads (and the reverse)
+// when lanes exchange data through LDS without a workgroup barrier.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Exchange term of an occupied band: ssx = e sigma, d ssx/d om = e delta.
@@ -159,7 +195,11 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
           double2 *__restrict__ grad_wt, double2 *__restrict__ grad_ieps,
           double2 *__restrict__ am_part)
 {
-    __shared__ double red[kBwdWaves][kChunk][2];
+    // Per-wave transpose slab for the daqsmtemp terms of up to kSlab bands
+    // (8 rows so that every lane's read below stays inside its wave's slab),
+    // and per-wave band sums awaiting the workgroup flush.
+    __shared__ double2 slab[kBwdWaves][kOctet][kWave];
+    __shared__ double2 red[kBwdWaves][kChunk];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const long blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -174,53 +214,73 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
     const cplx cw = cmake(ps.om.re, -ps.om.im);  // conj(om)
     const double2 *am_col = aqsm + p;
     const uint32_t goff = (uint32_t)gc * (uint32_t)sizeof(double2);
+    // transpose roles: lane = (band j of the slab, segment k of 8 lanes)
+    const int tj = lane >> 3, tk = lane & (kOctet - 1);
 
     cplx Ge = cmake(0.0, 0.0), Gw = cmake(0.0, 0.0);
     for (int c0 = 0; c0 < nb; c0 += kChunk) {
         const int c1 = c0 + kChunk < nb ? c0 + kChunk : nb;
-        int n = c0;
-        while (n < c1) {
-            // bands n .. n+cnt-1 form one batch-inverted group
-            const bool occ = n < nv;
-            const int cnt = (!occ && n + kBwdGroup <= c1 && n + kBwdGroup <= nb) ? kBwdGroup : 1;
-            cplx K[kBwdGroup], L[kBwdGroup];
-            if (cnt == kBwdGroup) {
-                ch_bands_kl<NW, kBwdGroup, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2,
-                                                 ps.thr, K, L);
-            } else {
-                cplx K1[1], L1[1];
-                ch_bands_kl<NW, 1, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr, K1, L1);
-                K[0] = K1[0];
-                L[0] = L1[0];
-            }
-#pragma unroll
-            for (int u = 0; u < kBwdGroup; ++u) {
-                if (u >= cnt) break;  // wave-uniform
-                const int nn = n + u;
-                cplx Z = cmul(cw, K[u]);
-                cplx W = L[u];
-                if (nn < nv) {
-                    cplx KS, LS;
-                    sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS, LS);
-                    Z = cadd(Z, KS);
-                    W = cadd(W, LS);
+        for (int b0 = c0; b0 < c1; b0 += kSlab) {
+            const int b1 = b0 + kSlab < c1 ? b0 + kSlab : c1;
+            int n = b0;
+            while (n < b1) {
+                // bands n .. n+cnt-1 form one batch-inverted group
+                const bool occ = n < nv;
+                const int cnt = (!occ && n + kBwdGroup <= b1) ? kBwdGroup : 1;
+                cplx K[kBwdGroup], L[kBwdGroup];
+                if (cnt == kBwdGroup) {
+                    ch_bands_kl<NW, kBwdGroup, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2,
+                                                     ps.thr, K, L);
+                } else {
+                    cplx K1[1], L1[1];
+                    ch_bands_kl<NW, 1, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr, K1,
+                                             L1);
+                    K[0] = K1[0];
+                    L[0] = L1[0];
                 }
-                const cplx an = load_row_elem(as_global(aqsn) + (size_t)nn * ng, ng, goff);
-                const cplx am = cload(am_col + (size_t)nn * ng);
-                const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
-                cmac(Ge, cM, Z);
-                cmac(Gw, cM, W);
-                if (am_part) {
-                    // this lane's term of daqsmtemp[nn][p]: ve an conj(Z)
-                    const cplx t = cmul(ps.ve, cmul_conj(an, Z));
-                    const double sr = wave_sum(t.re), si = wave_sum(t.im);
-                    if (lane == 0) {
-                        red[wid][nn - c0][0] = sr;
-                        red[wid][nn - c0][1] = si;
+#pragma unroll
+                for (int u = 0; u < kBwdGroup; ++u) {
+                    if (u >= cnt) break;  // wave-uniform
+                    const int nn = n + u;
+                    cplx Z = cmul(cw, K[u]);
+                    cplx W = L[u];
+                    if (nn < nv) {
+                        cplx KS, LS;
+                        sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS,
+                                       LS);
+                        Z = cadd(Z, KS);
+                        W = cadd(W, LS);
+                    }
+                    const cplx an = load_row_elem(as_global(aqsn) + (size_t)nn * ng, ng, goff);
+                    const cplx am = cload(am_col + (size_t)nn * ng);
+                    const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
+                    cmac(Ge, cM, Z);
+                    cmac(Gw, cM, W);
+                    if (am_part) {
+                        // this lane's term of daqsmtemp[nn][p]: ve an conj(Z)
+                        const cplx t = cmul(ps.ve, cmul_conj(an, Z));
+                        slab[wid][nn - b0][lane] = make_double2(t.re, t.im);
                     }
                 }
+                n += cnt;
             }
-            n += cnt;
+            if (am_part) {
+                // Row sums of the slab: lane (tj, tk) adds 8 entries of row tj
+                // (rotated so the 8 lanes of an octet hit distinct banks), then
+                // the octet adds its 8 partial sums.
+                wave_lds_sync();
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int i = 0; i < kOctet; ++i) {
+                    const double2 v = slab[wid][tj][kOctet * tk + ((i + tk + tj) & (kOctet - 1))];
+                    sr += v.x;
+                    si += v.y;
+                }
+                sr = octet_sum(sr);
+                si = octet_sum(si);
+                if (tk == 0 && tj < b1 - b0) red[wid][b0 - c0 + tj] = make_double2(sr, si);
+                wave_lds_sync();
+            }
         }
         if (am_part) {
             __syncthreads();
@@ -229,7 +289,10 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
                 const int j = t >> 1, c = t & 1;
                 double s = 0.0;
 #pragma unroll
-                for (int k = 0; k < kBwdWaves; ++k) s += red[k][j][c];
+                for (int k = 0; k < kBwdWaves; ++k) {
+                    const double2 v = red[k][j];
+                    s += c ? v.y : v.x;
+                }
                 double *dst = reinterpret_cast<double *>(
                     am_part + ((size_t)gb * nb + c0 + j) * np + p);
                 dst[c] = s;
@@ -252,33 +315,89 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
 }
 
 // ---- bands kernel: daqsntemp --------------------------------------------
+// Fast form of one wave's p loop: every band n0 .. n0+kBandTile-1 is
+// unoccupied and below nb.  With u_w = (x_w - om) r_w (r_w the masked
+// reciprocal of |x_w - om|^2),
+//   K = sum_w gh_w u_w = S - om R,  S = sum_w xgh_w r_w,  R = sum_w gh_w r_w,
+// so vcoul conj(e) Z = vcoul conj(e) conj(om) K = c1 S - c2 R with the
+// per-pair constants c1 = vcoul conj(e om) and c2 = vcoul conj(e) |om|^2.
 template <int NW>
-__global__ void __launch_bounds__(kBwdThreads)
-bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
-          const double2 *__restrict__ aqsm, const double2 *__restrict__ ieps,
-          const double2 *__restrict__ wt, const double *__restrict__ vcoul,
-          const double *__restrict__ wx, const double2 *__restrict__ gh,
-          const double2 *__restrict__ gs, double2 *__restrict__ grad_an)
+__device__ __forceinline__ void bands_fast(int nb, int ng, int np, int n0, int gc, double vc,
+                                           gptr<double2> aqsm, gptr<double2> ieps,
+                                           gptr<double2> wt, gptr<double> wx,
+                                           gptr<double2> gh, gptr<double2> xgh,
+                                           cplx (&acc)[kBandTile])
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const long tile = (long)xcd_remap(blockIdx.x, gridDim.x) * kBwdWaves + wid;
-    if (tile >= ntiles) return;  // wave-uniform; no barriers below
-    // band tile fastest: neighbouring waves share the g rows of wtilde/I_eps
-    const int gt = (int)(tile / nbt);
-    const int n0 = (int)(tile - (long)gt * nbt) * kBandTile;
-    const int g = gt * kWave + lane;
-    const bool valid = g < ng;
-    const int gc = valid ? g : ng - 1;
-
-    cplx acc[kBandTile];
+    constexpr int Kt = kBwdGroup * NW;
+    for (int p = 0; p < np; ++p) {
+        const int nfirst = opaque_uniform(n0);  // reload x and xgh per p
+        const cplx om = cload(wt + (size_t)p * ng + gc);
+        const cplx e = cload(ieps + (size_t)p * ng + gc);
+        const double a = om.re, b = om.im;
+        const double wi2 = b * b;
+        const double wtr = fma(a, a, wi2);
+        const double thr = branch_a_threshold(wtr);
+        const cplx vce = cmake(vc * e.re, -(vc * e.im));  // vcoul conj(e)
+        const cplx c1 = cmul(vce, cmake(a, -b));
+        const cplx c2 = cscale(wtr, vce);
 #pragma unroll
-    for (int u = 0; u < kBandTile; ++u) acc[u] = cmake(0.0, 0.0);
+        for (int u0 = 0; u0 < kBandTile; u0 += kBwdGroup) {
+            const int n = nfirst + u0;
+            double xs[Kt], dc[Kt], r[Kt];
+            bool isA[Kt];
+#pragma unroll
+            for (int u = 0; u < kBwdGroup; ++u)
+#pragma unroll
+                for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
+#pragma unroll
+            for (int k = 0; k < Kt; ++k) {
+                const double dr = xs[k] - a;
+                const double wd = fma(dr, dr, wi2);
+                isA[k] = wd > thr;
+                dc[k] = fmax(wd, kLimitTwo);
+            }
+            batch_reciprocal<Kt>(dc, r);
+#pragma unroll
+            for (int u = 0; u < kBwdGroup; ++u) {
+                cplx S = cmake(0.0, 0.0), R = cmake(0.0, 0.0);
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const int k = u * NW + w;
+                    const double re = mask_keep(isA[k], r[k]);
+                    const cplx xg = cload(xgh + (size_t)w * nb + n + u);
+                    const cplx g = cload(gh + w);
+                    S.re = fma(re, xg.re, S.re);
+                    S.im = fma(re, xg.im, S.im);
+                    R.re = fma(re, g.re, R.re);
+                    R.im = fma(re, g.im, R.im);
+                }
+                const cplx vZ = cmake(c1.re * S.re - c1.im * S.im - c2.re * R.re + c2.im * R.im,
+                                      c1.re * S.im + c1.im * S.re - c2.re * R.im - c2.im * R.re);
+                const cplx am = cload(aqsm + (size_t)(n + u) * ng + p);
+                cmac(acc[u0 + u], am, vZ);
+            }
+            // one group's reciprocal chain at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
 
+// Generic form: occupied bands (exchange terms) and a ragged last tile.
+template <int NW>
+__device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int np, int n0, int gc,
+                                              bool valid, const double2 *__restrict__ aqsm,
+                                              const double2 *__restrict__ ieps,
+                                              const double2 *__restrict__ wt,
+                                              const double *__restrict__ vcoul,
+                                              const double *__restrict__ wx,
+                                              const double2 *__restrict__ gh,
+                                              const double2 *__restrict__ gs,
+                                              cplx (&acc)[kBandTile])
+{
     for (int p = 0; p < np; ++p) {
         const PairState ps = load_pair(wt, ieps, vcoul, p, ng, gc, valid);
-        const cplx cw = cmake(ps.om.re, -ps.om.im);
-        const cplx vce = cmake(ps.ve.re, -ps.ve.im);  // vcoul conj(e)
+        const cplx vce = cmake(ps.ve.re, -ps.ve.im);           // vcoul conj(e)
+        const cplx vcw = cmul(vce, cmake(ps.om.re, -ps.om.im));  // vcoul conj(e om)
 #pragma unroll
         for (int u0 = 0; u0 < kBandTile; u0 += kBwdGroup) {
             const int n = n0 + u0;
@@ -304,18 +423,50 @@ bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
             for (int u = 0; u < kBwdGroup; ++u) {
                 const int nn = n + u;
                 if (nn < nb) {
-                    cplx Z = cmul(cw, K[u]);
+                    // vcoul conj(e) Z = vcoul conj(e om) K [+ vcoul conj(e) KS]
+                    cplx vZ = cmul(vcw, K[u]);
                     if (nn < nv) {
                         cplx KS, LS;
                         sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS, LS);
-                        Z = cadd(Z, KS);
+                        cmac(vZ, vce, KS);
                     }
                     const cplx am = cload(aqsm + (size_t)nn * ng + p);
-                    cmac(acc[u0 + u], am, cmul(vce, Z));
+                    cmac(acc[u0 + u], am, vZ);
                 }
             }
         }
     }
+}
+
+template <int NW>
+__global__ void __launch_bounds__(kBwdThreads)
+bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
+          const double2 *__restrict__ aqsm, const double2 *__restrict__ ieps,
+          const double2 *__restrict__ wt, const double *__restrict__ vcoul,
+          const double *__restrict__ wx, const double2 *__restrict__ gh,
+          const double2 *__restrict__ xgh, const double2 *__restrict__ gs,
+          double2 *__restrict__ grad_an)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const long tile = (long)xcd_remap(blockIdx.x, gridDim.x) * kBwdWaves + wid;
+    if (tile >= ntiles) return;  // wave-uniform; no barriers below
+    // band tile fastest: neighbouring waves share the g rows of wtilde/I_eps
+    const int gt = (int)(tile / nbt);
+    const int n0 = (int)(tile - (long)gt * nbt) * kBandTile;
+    const int g = gt * kWave + lane;
+    const bool valid = g < ng;
+    const int gc = valid ? g : ng - 1;
+
+    cplx acc[kBandTile];
+#pragma unroll
+    for (int u = 0; u < kBandTile; ++u) acc[u] = cmake(0.0, 0.0);
+    if (n0 >= nv && n0 + kBandTile <= nb)
+        bands_fast<NW>(nb, ng, np, n0, gc, valid ? vcoul[gc] : 0.0, as_global(aqsm),
+                       as_global(ieps), as_global(wt), as_global(wx), as_global(gh),
+                       as_global(xgh), acc);
+    else
+        bands_generic<NW>(nb, nv, ng, np, n0, gc, valid, aqsm, ieps, wt, vcoul, wx, gh, gs, acc);
     if (valid) {
 #pragma unroll
         for (int u = 0; u < kBandTile; ++u) {
@@ -401,7 +552,7 @@ static hipError_t launch_bwd_nw(const Dims32 &d, const BwdGeometry &geo, const D
     if (out.grad_an) {
         hipLaunchKernelGGL(bwd_bands<NW>, dim3((unsigned)geo.band_blocks), dim3(kBwdThreads), 0,
                            st, d.nb, d.nv, d.ng, d.np, geo.band_tiles, geo.nbt, in.aqsm, in.ieps,
-                           in.wt, in.vcoul, in.wx, gh, gs, out.grad_an);
+                           in.wt, in.vcoul, in.wx, gh, xgh, gs, out.grad_an);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

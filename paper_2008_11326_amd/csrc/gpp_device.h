@@ -45,6 +45,17 @@ __device__ __forceinline__ cplx cload(const double2 *p) {
     double2 v = *p;
     return {v.x, v.y};
 }
+// The same wave-uniform integer, opaque to the optimiser: loads indexed by
+// it cannot be hoisted out of the loop that calls this.  Used where
+// wave-uniform values would otherwise be hoisted into more scalar registers
+// than exist (and spilled into vector lanes); reloading them each iteration
+// goes through the scalar cache instead.  The base pointer stays visible,
+// so the loads remain scalar loads.
+__device__ __forceinline__ int opaque_uniform(int v) {
+    asm volatile("" : "+s"(v));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 __device__ __forceinline__ cplx cload(gptr<double2> p) {
     return {p->x, p->y};  // member reads: one 16-byte load after vectorising
 }

@@ -8,6 +8,7 @@ Si-system run: number_bands=512, nvband=2, ncouls=32768, ngpown=1638,
 nfreq=3, inputs resident in HBM.  Prints one JSON line on stdout.
 
     python bench.py [--steps K] [--warmup W] [--workload si|small|adjoint|large]
+    python bench.py --leg adjoint|batched     # one leg alone, for profiling
 
 Throughput is algorithmic: 21 fp64 operations per Coulomb-hole term plus
 21 per screened-exchange term (the arithmetic the method needs, fixed
@@ -174,6 +175,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint and batched legs")
+    ap.add_argument("--leg", choices=("all", "adjoint", "batched"), default="all",
+                    help="adjoint or batched: run only that leg and print its JSON "
+                         "(for per-kernel profiling); all: the benchmark line")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -191,6 +195,12 @@ def main():
     from paper_2008_11326_amd import inputs as I
 
     _lib.load()  # fail loudly if the HIP library is missing
+    if args.leg != "all":
+        stream = torch.cuda.current_stream(torch.device("cuda:0"))
+        leg = adjoint_leg if args.leg == "adjoint" else batched_leg
+        log(f"[bench] {args.leg} leg only")
+        print(json.dumps({"leg": args.leg, **leg(gpp, I, stream)}), flush=True)
+        return
     wl = I.WORKLOADS[args.workload]
     d = wl.dims
     log(f"[bench] generating {wl.name}")

@@ -3,7 +3,10 @@
 //
 // The tiles of all states (each state's forward tiles: one G' column x 64
 // G rows, G'-column fastest) are concatenated in a schedule order chosen by
-// the plan.  Persistent wave w takes global tiles w, w + W, w + 2W, ...
+// the plan.  Two kernel forms exist: the static one below and a work-queue
+// one (batched_queue) whose waves take small chunks of the list from atomic
+// counters.  In the static form, persistent wave w takes global tiles
+// w, w + W, w + 2W, ...
 // (W = resident waves), so at any moment the running waves sit on
 // neighbouring tiles of one state -- the same aqsntemp rows and L2
 // locality as the plain forward -- and every wave's cost stays within one

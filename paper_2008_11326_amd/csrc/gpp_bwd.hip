@@ -39,6 +39,17 @@ constexpr int kBwdGroup = 3;                       // bands per batch-inverted g
 constexpr int kChunk = 48;                         // bands per LDS flush (multiple of kSlab)
 constexpr int kSlab = 6;                           // bands per in-wave transpose (two groups)
 constexpr int kOctet = 8;                          // lanes that share one band's row sum
+// Minimum waves per SIMD the compiler must allow (register cap) for the
+// pairs and bands kernels; 1 leaves the allocation to the compiler.  The
+// defaults (pairs 4 waves = 128 VGPRs with a few spills outside the band
+// loop, bands 5 waves = 96 VGPRs) each measured about 1.3 % faster on the
+// nb256/ng16384/np819 adjoint workload than the compiler's own choice.
+#ifndef GPP_BWD_PAIRS_WAVES
+#define GPP_BWD_PAIRS_WAVES 4
+#endif
+#ifndef GPP_BWD_BANDS_WAVES
+#define GPP_BWD_BANDS_WAVES 5
+#endif
 #ifndef GPP_BWD_BAND_TILE
 #define GPP_BWD_BAND_TILE 3
 #endif
@@ -115,7 +126,8 @@ template <int NW, int BU, bool WANT_L>
 __device__ __forceinline__ void ch_bands_kl(int n, int nb, const double *__restrict__ wx,
                                             const double2 *__restrict__ gh,
                                             const double2 *__restrict__ xgh, double a, double b,
-                                            double wi2, double thr, cplx (&K)[BU], cplx (&L)[BU])
+                                            double wi2, double thr, bool wide, cplx (&K)[BU],
+                                            cplx (&L)[BU])
 {
     constexpr int Kt = BU * NW;
     double xs[Kt], dc[Kt], drs[Kt], r[Kt];
@@ -129,9 +141,9 @@ __device__ __forceinline__ void ch_bands_kl(int n, int nb, const double *__restr
         drs[k] = xs[k] - a;
         const double wd = fma(drs[k], drs[k], wi2);
         isA[k] = wd > thr;
-        dc[k] = fmax(wd, kLimitTwo);
+        dc[k] = wd;  // unclamped: see batch_reciprocal
     }
-    batch_reciprocal<Kt>(dc, r);
+    batch_reciprocal<Kt>(dc, r, wide);
 #pragma unroll
     for (int u = 0; u < BU; ++u) {
         K[u] = L[u] = cmake(0.0, 0.0);
@@ -165,6 +177,7 @@ __device__ __forceinline__ void sx_band_kl(int n, int nb, const double *__restri
 
 struct PairState {
     double a, b, wi2, wtr, thr;
+    bool wide;  // (Im om)^2 >= kMinUnclampedWi2: batch inversion allowed
     cplx om, e, ve;  // ve = vcoul[g] e (0 for rows beyond ncouls)
 };
 
@@ -180,6 +193,7 @@ __device__ __forceinline__ PairState load_pair(const double2 *wt, const double2 
     s.wi2 = s.b * s.b;
     s.wtr = fma(s.a, s.a, s.wi2);
     s.thr = branch_a_threshold(s.wtr);
+    s.wide = s.wi2 >= kMinUnclampedWi2;
     s.ve = cscale(valid ? vcoul[gc] : 0.0, s.e);
     return s;
 }
@@ -187,6 +201,7 @@ __device__ __forceinline__ PairState load_pair(const double2 *wt, const double2 
 // ---- pairs kernel: dwtilde, dI_eps and daqsmtemp partials -----------------
 template <int NW>
 __global__ void __launch_bounds__(kBwdThreads)
+__attribute__((amdgpu_waves_per_eu(GPP_BWD_PAIRS_WAVES)))
 bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restrict__ aqsm,
           const double2 *__restrict__ aqsn, const double2 *__restrict__ ieps,
           const double2 *__restrict__ wt, const double *__restrict__ vcoul,
@@ -230,11 +245,11 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
                 cplx K[kBwdGroup], L[kBwdGroup];
                 if (cnt == kBwdGroup) {
                     ch_bands_kl<NW, kBwdGroup, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2,
-                                                     ps.thr, K, L);
+                                                     ps.thr, ps.wide, K, L);
                 } else {
                     cplx K1[1], L1[1];
-                    ch_bands_kl<NW, 1, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr, K1,
-                                             L1);
+                    ch_bands_kl<NW, 1, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr,
+                                             ps.wide, K1, L1);
                     K[0] = K1[0];
                     L[0] = L1[0];
                 }
@@ -337,6 +352,7 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int np, int n0, int g
         const double wi2 = b * b;
         const double wtr = fma(a, a, wi2);
         const double thr = branch_a_threshold(wtr);
+        const bool wide = wi2 >= kMinUnclampedWi2;
         const cplx vce = cmake(vc * e.re, -(vc * e.im));  // vcoul conj(e)
         const cplx c1 = cmul(vce, cmake(a, -b));
         const cplx c2 = cscale(wtr, vce);
@@ -354,9 +370,9 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int np, int n0, int g
                 const double dr = xs[k] - a;
                 const double wd = fma(dr, dr, wi2);
                 isA[k] = wd > thr;
-                dc[k] = fmax(wd, kLimitTwo);
+                dc[k] = wd;  // unclamped: see batch_reciprocal
             }
-            batch_reciprocal<Kt>(dc, r);
+            batch_reciprocal<Kt>(dc, r, wide);
 #pragma unroll
             for (int u = 0; u < kBwdGroup; ++u) {
                 cplx S = cmake(0.0, 0.0), R = cmake(0.0, 0.0);
@@ -406,7 +422,7 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int np, in
             const bool full = n + kBwdGroup <= nb && n >= nv;
             if (full) {
                 ch_bands_kl<NW, kBwdGroup, false>(n, nb, wx, gh, nullptr, ps.a, ps.b, ps.wi2,
-                                                  ps.thr, K, L);
+                                                  ps.thr, ps.wide, K, L);
             } else {
 #pragma unroll
                 for (int u = 0; u < kBwdGroup; ++u) {
@@ -414,7 +430,7 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int np, in
                     if (n + u < nb) {
                         cplx K1[1], L1[1];
                         ch_bands_kl<NW, 1, false>(n + u, nb, wx, gh, nullptr, ps.a, ps.b,
-                                                  ps.wi2, ps.thr, K1, L1);
+                                                  ps.wi2, ps.thr, ps.wide, K1, L1);
                         K[u] = K1[0];
                     }
                 }
@@ -440,6 +456,7 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int np, in
 
 template <int NW>
 __global__ void __launch_bounds__(kBwdThreads)
+__attribute__((amdgpu_waves_per_eu(GPP_BWD_BANDS_WAVES)))
 bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
           const double2 *__restrict__ aqsm, const double2 *__restrict__ ieps,
           const double2 *__restrict__ wt, const double *__restrict__ vcoul,

@@ -22,6 +22,10 @@ constexpr double kTolZero = 1e-12;
 // kLimitOne * kLimitTwo, exact.  For wtr below it, A <=> wdiffr > kLimitTwo:
 // rounding is monotone, so wdiffr > 1/4 gives fl(kLimitOne*wdiffr) >= 62500.
 constexpr double kFastWtr = 62500.0;
+// Smallest (Im om)^2 for which the batch inversion may take the CH
+// denominators unclamped: every |x - om|^2 >= (Im om)^2 >= 2^-60, so a
+// product of up to 12 of them stays >= 2^-720, far from underflow.
+constexpr double kMinUnclampedWi2 = 0x1p-60;
 
 constexpr int kWave = 64;
 
@@ -94,19 +98,24 @@ __device__ __forceinline__ double rcp_nr2(double d) {
     return r;
 }
 
-// Batch inversion: r[k] = 1/d[k] for K values with d[k] >= 1/4, from one
-// reciprocal of their product.  Prefix products c[k] = d[0]...d[k]; then
-// R = 1/c[K-1] and, walking back, r[k] = R c[k-1] and R <- R d[k].  Costs
-// 3(K-1) multiplies plus one rcp_nr2 instead of K of them; each r[k]
-// carries at most 2K roundings.  A lane whose product would overflow
-// (some d above ~2^(1000/K)) takes the one-by-one path instead.
+// Batch inversion: r[k] = 1/d[k] for K positive values from one reciprocal
+// of their product.  Prefix products c[k] = d[0]...d[k]; then R = 1/c[K-1]
+// and, walking back, r[k] = R c[k-1] and R <- R d[k].  Costs 3(K-1)
+// multiplies plus one rcp_nr2 instead of K of them; each r[k] carries at
+// most 2K roundings.  The batch path needs every d[k] >= 2^-60 (so that no
+// prefix product, K <= 12, leaves the normal range at the bottom; callers
+// pass batch_ok = false for a lane without that bound) and c[K-1] < 2^1000
+// (an overflowed prefix stays infinite, so this also covers the middle
+// ones).  Other lanes take the one-by-one path; a zero there gives an
+// infinite or NaN reciprocal, which callers mask.
 template <int K>
-__device__ __forceinline__ void batch_reciprocal(const double (&d)[K], double (&r)[K]) {
+__device__ __forceinline__ void batch_reciprocal(const double (&d)[K], double (&r)[K],
+                                                 bool batch_ok = true) {
     double c[K];
     c[0] = d[0];
 #pragma unroll
     for (int k = 1; k < K; ++k) c[k] = c[k - 1] * d[k];
-    if (__builtin_expect(c[K - 1] < 0x1p1000, 1)) {
+    if (__builtin_expect(batch_ok && c[K - 1] < 0x1p1000, 1)) {
         double R = rcp_nr2(c[K - 1]);
 #pragma unroll
         for (int k = K - 1; k > 0; --k) {

@@ -11,12 +11,15 @@ namespace gpp {
 // CH-only accumulation for BU consecutive unoccupied bands starting at n.
 // aqsntemp[n][g] is read through a buffer descriptor for the row (scalar
 // registers) plus the lane's 32-bit byte offset, so the per-band address
-// arithmetic stays on the scalar unit.
+// arithmetic stays on the scalar unit.  The denominators go into the batch
+// inversion unclamped: every one is at least (Im om)^2, and a lane with
+// (Im om)^2 below kMinUnclampedWi2 (wide == false) inverts one by one; a
+// masked term's reciprocal (possibly infinite or NaN there) is cleared.
 template <int NW, int BU>
 __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aqsn,
                                          uint32_t goff, gptr<double2> am_col,
                                          gptr<double> wx, double a, double wi2, double thr,
-                                         cplx (&P1)[NW], cplx (&P2)[NW])
+                                         bool wide, cplx (&P1)[NW], cplx (&P2)[NW])
 {
     constexpr int K = BU * NW;
     cplx qm[BU];
@@ -35,9 +38,9 @@ __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aq
         const double dr = xs[k] - a;
         const double wd = fma(dr, dr, wi2);
         isA[k] = wd > thr;
-        dc[k] = fmax(wd, kLimitTwo);
+        dc[k] = wd;
     }
-    batch_reciprocal<K>(dc, r);
+    batch_reciprocal<K>(dc, r, wide);
 #pragma unroll
     for (int u = 0; u < BU; ++u) {
 #pragma unroll
@@ -128,11 +131,12 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
     }
 
     // unoccupied bands: CH only -- the hot loop
+    const bool wide = wi2 >= kMinUnclampedWi2;
     int n = nv;
     for (; n + BU <= nb; n += BU)
-        ch_group<NW, BU>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, P1, P2);
+        ch_group<NW, BU>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
     for (; n < nb; ++n)
-        ch_group<NW, 1>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, P1, P2);
+        ch_group<NW, 1>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
 
 #pragma unroll
     for (int w = 0; w < NW; ++w) {

@@ -53,3 +53,21 @@ def load_golden(key):
     rec["ach"] = c(rec["achtemp"])
     rec["asx"] = c(rec["asxtemp"])
     return rec
+
+
+def mixed_pole_problem(seed, dims, frac):
+    """A problem whose tiles mix lanes with (Im om)^2 below 2^-60 (real om,
+    or |Im om| ~ 1e-10) and ordinary lanes; a fifth of the real ones sit
+    exactly on a frequency (x == om, a zero denominator).  Such lanes invert
+    their denominators one by one in the kernels."""
+    from paper_2008_11326_amd import inputs as I
+    prob = I.make_problem(dims, seed)
+    rng = np.random.default_rng(seed)
+    wt = prob.wtilde_array
+    low = rng.random(wt.shape) < frac
+    tiny = low & (rng.random(wt.shape) < 0.3)
+    wt.imag[low] = 0.0
+    wt.imag[tiny] = rng.uniform(-1e-10, 1e-10, int(tiny.sum()))
+    pole = low & ~tiny & (rng.random(wt.shape) < 0.2)
+    wt.real[pole] = rng.choice(prob.wx_array.ravel(), size=int(pole.sum()))
+    return prob

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2008_11326_amd import inputs as I
-from tests.gpu_helpers import assert_parity, load_golden, say, to_device
+from tests.gpu_helpers import assert_parity, load_golden, mixed_pole_problem, say, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -55,6 +55,24 @@ def test_uneven_states_vs_oracle_and_plain(gpp, uneven, tmp_path, monkeypatch):
         for got, plain in ((ach[k].cpu().numpy(), g[0]), (asx[k].cpu().numpy(), g[1])):
             scale = np.abs(plain) + 1e-300
             assert np.all(np.abs(got - plain) <= 1e-12 * scale + 1e-300)
+    plan.close()
+
+
+def test_tiny_imaginary_lanes(gpp, tmp_path, monkeypatch):
+    """States whose tiles mix lanes with (Im om)^2 below 2^-60 (one-by-one
+    reciprocals, exact poles) with ordinary lanes, against the oracle."""
+    import torch
+    monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    probs = [mixed_pole_problem(50 + k, d, f) for k, (d, f) in enumerate(
+        [(I.Dims(20, 2, 300, 7, 3), 0.5), (I.Dims(11, 2, 129, 5, 3), 1.0),
+         (I.Dims(30, 2, 500, 12, 3), 0.05)])]
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    ach, asx = gpp.sigma_batched(plan, [to_device(p) for p in probs])
+    torch.cuda.synchronize()
+    for k, p in enumerate(probs):
+        ref = oracle.sigma_fwd(p)
+        assert_parity(ach[k].cpu().numpy(), ref[0], ref[2], f"state {k} achtemp")
+        assert_parity(asx[k].cpu().numpy(), ref[1], ref[3], f"state {k} asxtemp")
     plan.close()
 
 

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2008_11326_amd import inputs as I
-from tests.gpu_helpers import say, to_device
+from tests.gpu_helpers import mixed_pole_problem, say, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,21 @@ def test_every_entry_small(gpp, shape, poles):
     check_entries("I_eps_array", g["I_eps_array"], prob, ga, gs, all_entries(npw, ng))
     check_entries("wtilde_array", g["wtilde_array"], prob, ga, gs, all_entries(npw, ng))
     assert np.all(g["aqsmtemp"][:, npw:] == 0)
+
+
+@pytest.mark.parametrize("frac", [0.05, 0.5, 1.0])
+def test_every_entry_tiny_imaginary_lanes(gpp, frac):
+    """Lanes whose (Im om)^2 is below 2^-60 (real om, exact poles, |Im om|
+    ~ 1e-10) mixed with ordinary ones inside the same tiles."""
+    prob = mixed_pole_problem(43, I.Dims(9, 2, 150, 4, 3), frac)
+    ga, gs = I.make_upstream_grad(3, np.random.default_rng(8))
+    say(f"[bwd] tiny-Im lanes {frac}")
+    g = gpu_grads(gpp, prob, ga, gs)
+    nb, _, ng, npw, _ = prob.dims.as_tuple()
+    check_entries("aqsmtemp", g["aqsmtemp"], prob, ga, gs, all_entries(nb, ng))
+    check_entries("aqsntemp", g["aqsntemp"], prob, ga, gs, all_entries(nb, ng))
+    check_entries("I_eps_array", g["I_eps_array"], prob, ga, gs, all_entries(npw, ng))
+    check_entries("wtilde_array", g["wtilde_array"], prob, ga, gs, all_entries(npw, ng))
 
 
 def test_skipped_outputs_and_determinism(gpp):

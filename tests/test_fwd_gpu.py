@@ -10,7 +10,8 @@ import pytest
 
 import oracle
 from paper_2008_11326_amd import inputs as I
-from tests.gpu_helpers import GOLDEN, assert_parity, load_golden, say, to_device
+from tests.gpu_helpers import (GOLDEN, assert_parity, load_golden, mixed_pole_problem, say,
+                               to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +95,12 @@ def test_slow_threshold_path(gpp):
               for om in prob.wtilde_array.ravel()[:50]]
     assert 0 in ref_br and 1 in ref_br
     check(gpp, prob, "slow threshold path")
+
+
+@pytest.mark.parametrize("frac", [0.05, 0.5, 1.0])
+def test_tiny_imaginary_lanes_and_exact_poles(gpp, frac):
+    prob = mixed_pole_problem(41, I.Dims(20, 2, 300, 7, 3), frac)
+    check(gpp, prob, f"tiny-Im lanes {frac}", nthreads=1)
 
 
 def test_empty_dimensions(gpp):

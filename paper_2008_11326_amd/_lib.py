@@ -69,6 +69,13 @@ _SIGNATURES = [
     ("gpp_status_string", C.c_char_p, [C.c_int]),
     ("gpp_last_error", C.c_char_p, []),
     ("gpp_version", C.c_int, []),
+    # include/gpp_ladder.h
+    ("gpp_ladder_steps", C.c_int32, []),
+    ("gpp_ladder_name", C.c_char_p, [C.c_int32]),
+    ("gpp_ladder_workspace", C.c_size_t, [C.c_int32, C.POINTER(GppDims)]),
+    ("gpp_ladder_fwd", C.c_int,
+     [C.c_int32, C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p,
+      C.c_void_p, C.c_size_t, C.c_void_p]),
     # include/gpp_microbench.h
     ("gpp_mb_fp64_fma", C.c_int,
      [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),

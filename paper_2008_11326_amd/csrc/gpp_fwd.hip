@@ -184,6 +184,47 @@ static hipError_t launch_fwd_nw(const Dims32 &d, const FwdGeometry &geo, const D
     return hipGetLastError();
 }
 
+size_t reduce_stage_bytes(int nw, long nrows)
+{
+    const long blocks = nrows < kRedBlocks ? nrows : kRedBlocks;
+    return (size_t)blocks * 4 * sizeof(double) * nw;
+}
+
+template <int NW>
+static hipError_t launch_reduce_nw(const double *partials, long nrows, double *stage,
+                                   double2 *ach, double2 *asx, hipStream_t st)
+{
+    const long blocks = nrows < kRedBlocks ? nrows : kRedBlocks;
+    const long chunk = (nrows + blocks - 1) / blocks;
+    hipLaunchKernelGGL(reduce_rows<NW>, dim3((unsigned)blocks), dim3(kRedThreads), 0, st,
+                       partials, nrows, chunk, stage, ach, asx, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_rows<NW>, dim3(1), dim3(kRedThreads), 0, st, stage, blocks,
+                       blocks, nullptr, ach, asx, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(int nw, const double *partials, long nrows, double *stage,
+                                  double2 *ach, double2 *asx, hipStream_t st)
+{
+    if (nrows <= 0) {
+        hipLaunchKernelGGL(fill_zero, dim3(1), dim3(64), 0, st, ach, asx, nw);
+        return hipGetLastError();
+    }
+    switch (nw) {
+    case 1: return launch_reduce_nw<1>(partials, nrows, stage, ach, asx, st);
+    case 2: return launch_reduce_nw<2>(partials, nrows, stage, ach, asx, st);
+    case 3: return launch_reduce_nw<3>(partials, nrows, stage, ach, asx, st);
+    case 4: return launch_reduce_nw<4>(partials, nrows, stage, ach, asx, st);
+    case 5: return launch_reduce_nw<5>(partials, nrows, stage, ach, asx, st);
+    case 6: return launch_reduce_nw<6>(partials, nrows, stage, ach, asx, st);
+    case 7: return launch_reduce_nw<7>(partials, nrows, stage, ach, asx, st);
+    case 8: return launch_reduce_nw<8>(partials, nrows, stage, ach, asx, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_fwd(const Dims32 &d, const DevInputs &in, double2 *ach, double2 *asx,
                       void *workspace, hipStream_t st)
 {

@@ -91,6 +91,12 @@ FwdGeometry fwd_geometry(const Dims32 &d);
 BwdGeometry bwd_geometry(const Dims32 &d);
 hipError_t launch_bwd(const Dims32 &d, const DevInputs &in, const double2 *ga,
                       const double2 *gs, const BwdOutputs &out, void *workspace, hipStream_t st);
+// Fixed-order two-stage sum of nrows partial rows of 4*nw doubles (achtemp
+// re/im, asxtemp re/im per frequency) into achtemp/asxtemp; the first stage
+// writes reduce_stage_bytes(nw, nrows) bytes to stage.
+size_t reduce_stage_bytes(int nw, long nrows);
+hipError_t launch_reduce_partials(int nw, const double *partials, long nrows, double *stage,
+                                  double2 *ach, double2 *asx, hipStream_t st);
 hipError_t launch_fwd(const Dims32 &d, const DevInputs &in, double2 *ach, double2 *asx,
                       void *workspace, hipStream_t st);
 

@@ -176,3 +176,42 @@ def test_plan_validation_before_any_device_call(lib):
     info = _lib.GppPlanInfo()
     assert lib.gpp_plan_get_info(None, C.byref(info)) == 1
     lib.gpp_plan_destroy(None)  # no-op
+
+
+def _ladder_call(lib, step, dims, ins=None, ws_bytes=None, ws=FAKE + 0x700000):
+    ins = _inputs() if ins is None else ins
+    need = lib.gpp_ladder_workspace(step, C.byref(dims))
+    ws_bytes = need if ws_bytes is None else ws_bytes
+    return lib.gpp_ladder_fwd(step, C.byref(dims), C.byref(ins), C.c_void_p(FAKE + 0x600000),
+                              C.c_void_p(FAKE + 0x600100), C.c_void_p(ws), ws_bytes, None)
+
+
+def test_ladder_names_and_validation(lib):
+    n = lib.gpp_ladder_steps()
+    assert n == 10
+    names = [lib.gpp_ladder_name(s).decode() for s in range(n)]
+    assert [s[:2] for s in names[:9]] == [f"v{k}" for k in range(9)]
+    assert "production" in names[9]
+    assert lib.gpp_ladder_name(-1) is None and lib.gpp_ladder_name(n) is None
+    d = _dims()
+    for bad in (-1, n):
+        assert lib.gpp_ladder_workspace(bad, C.byref(d)) == 0
+        assert _ladder_call(lib, bad, d, ws_bytes=256) == 1
+        assert "step" in lib.gpp_last_error().decode()
+    # steps 0-8 take nfreq <= 4; the production step takes up to 8
+    d5 = _dims(nw=5)
+    for step in range(9):
+        assert lib.gpp_ladder_workspace(step, C.byref(d5)) == 0
+        assert _ladder_call(lib, step, d5, ws_bytes=1 << 20) == 1
+        assert "nfreq" in lib.gpp_last_error().decode()
+    assert lib.gpp_ladder_workspace(9, C.byref(d5)) == lib.gpp_sigma_fwd_workspace(C.byref(d5))
+    for step in range(9):
+        assert lib.gpp_ladder_workspace(step, C.byref(d)) > 0
+        assert _ladder_call(lib, step, d, ins=_inputs(aqsntemp=0)) == 1
+        assert _ladder_call(lib, step, d, ws=0) == 4
+        assert _ladder_call(lib, step, d, ws_bytes=lib.gpp_ladder_workspace(step, C.byref(d)) - 1) == 4
+        assert "workspace" in lib.gpp_last_error().decode()
+    # the transposed aqsmtemp copy of steps 7-8 lives in the workspace
+    big = _dims(nb=512, ng=32768, npw=1638)
+    assert lib.gpp_ladder_workspace(7, C.byref(big)) >= \
+        lib.gpp_ladder_workspace(6, C.byref(big)) + 512 * 1638 * 16

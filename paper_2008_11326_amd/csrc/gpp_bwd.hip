@@ -344,10 +344,15 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int np, int n0, int g
                                            cplx (&acc)[kBandTile])
 {
     constexpr int Kt = kBwdGroup * NW;
+    // om and e of the next column are loaded one iteration ahead, so their
+    // latency overlaps this column's arithmetic
+    cplx om_next = cload(wt + gc), e_next = cload(ieps + gc);
     for (int p = 0; p < np; ++p) {
         const int nfirst = opaque_uniform(n0);  // reload x and xgh per p
-        const cplx om = cload(wt + (size_t)p * ng + gc);
-        const cplx e = cload(ieps + (size_t)p * ng + gc);
+        const cplx om = om_next, e = e_next;
+        const int pn = p + 1 < np ? p + 1 : p;
+        om_next = cload(wt + (size_t)pn * ng + gc);
+        e_next = cload(ieps + (size_t)pn * ng + gc);
         const double a = om.re, b = om.im;
         const double wi2 = b * b;
         const double wtr = fma(a, a, wi2);

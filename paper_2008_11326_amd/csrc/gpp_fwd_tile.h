@@ -6,6 +6,10 @@
 
 #include "gpp_device.h"
 
+#ifndef GPP_FWD_PREFETCH
+#define GPP_FWD_PREFETCH 0
+#endif
+
 namespace gpp {
 
 // CH-only accumulation for BU consecutive unoccupied bands starting at n.
@@ -15,11 +19,20 @@ namespace gpp {
 // inversion unclamped: every one is at least (Im om)^2, and a lane with
 // (Im om)^2 below kMinUnclampedWi2 (wide == false) inverts one by one; a
 // masked term's reciprocal (possibly infinite or NaN there) is cleared.
+// The group's aqsntemp values of this lane (one per band).
+template <int BU>
+__device__ __forceinline__ void load_an(int n, int ng, gptr<double2> aqsn, uint32_t goff,
+                                        cplx (&an)[BU])
+{
+#pragma unroll
+    for (int u = 0; u < BU; ++u) an[u] = load_row_elem(aqsn + (size_t)(n + u) * ng, ng, goff);
+}
+
 template <int NW, int BU>
-__device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aqsn,
-                                         uint32_t goff, gptr<double2> am_col,
-                                         gptr<double> wx, double a, double wi2, double thr,
-                                         bool wide, cplx (&P1)[NW], cplx (&P2)[NW])
+__device__ __forceinline__ void ch_group_an(int n, int nb, int ng, const cplx (&an)[BU],
+                                            gptr<double2> am_col, gptr<double> wx, double a,
+                                            double wi2, double thr, bool wide, cplx (&P1)[NW],
+                                            cplx (&P2)[NW])
 {
     constexpr int K = BU * NW;
     cplx qm[BU];
@@ -27,9 +40,8 @@ __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aq
     bool isA[K];
 #pragma unroll
     for (int u = 0; u < BU; ++u) {
-        const cplx an = load_row_elem(aqsn + (size_t)(n + u) * ng, ng, goff);
         const cplx am = cload(am_col + (size_t)(n + u) * ng);
-        qm[u] = cmul_conj(an, am);
+        qm[u] = cmul_conj(an[u], am);
 #pragma unroll
         for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
     }
@@ -54,6 +66,17 @@ __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aq
             P2[w].im = fma(re, qm[u].im, P2[w].im);
         }
     }
+}
+
+template <int NW, int BU>
+__device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aqsn,
+                                         uint32_t goff, gptr<double2> am_col,
+                                         gptr<double> wx, double a, double wi2, double thr,
+                                         bool wide, cplx (&P1)[NW], cplx (&P2)[NW])
+{
+    cplx an[BU];
+    load_an<BU>(n, ng, aqsn, goff, an);
+    ch_group_an<NW, BU>(n, nb, ng, an, am_col, wx, a, wi2, thr, wide, P1, P2);
 }
 
 // One tile: lane g = gt*64 + lane of column p.  On return ach[w] holds this
@@ -133,8 +156,24 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
     // unoccupied bands: CH only -- the hot loop
     const bool wide = wi2 >= kMinUnclampedWi2;
     int n = nv;
+#if GPP_FWD_PREFETCH
+    // the next group's aqsntemp values are loaded while this group computes
+    // (the last group reloads its own rows, so every load stays in range)
+    if (n + BU <= nb) {
+        cplx an[BU];
+        load_an<BU>(n, ng, aqsn, goff, an);
+        for (; n + BU <= nb; n += BU) {
+            cplx an_next[BU];
+            load_an<BU>(n + 2 * BU <= nb ? n + BU : n, ng, aqsn, goff, an_next);
+            ch_group_an<NW, BU>(n, nb, ng, an, am_col, wx, a, wi2, thr, wide, P1, P2);
+#pragma unroll
+            for (int u = 0; u < BU; ++u) an[u] = an_next[u];
+        }
+    }
+#else
     for (; n + BU <= nb; n += BU)
         ch_group<NW, BU>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
+#endif
     for (; n < nb; ++n)
         ch_group<NW, 1>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
 

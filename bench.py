@@ -76,13 +76,30 @@ def cpu_baseline(prob, target_seconds):
     oracle.sigma_fwd_slice(prob, p=(0, k), nthreads=threads)
     dt = time.perf_counter() - t0
     terms = k * per_col
+    # one thread on one column, for the per-core rate
+    t0 = time.perf_counter()
+    oracle.sigma_fwd_slice(prob, p=(0, 1), nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {
         "value": FLOP_PER_TERM * terms / dt / 1e12, "unit": "TFLOP/s",
         "cores": min(threads, k), "kind": "oracle",
         "sample": f"G' columns p in [0,{k}) of {d.ngpown}, all {d.number_bands} bands "
                   f"and {d.ncouls} rows, nfreq={d.nfreq}: {terms:.3e} terms in {dt:.1f} s",
         "terms_per_s": terms / dt,
+        "single_thread_terms_per_s": per_col / dt1,
+        "cpu_model": _cpu_model(),
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def timed_ms(fn, stream, reps):

@@ -53,6 +53,11 @@ def _check_tensor(name, t, dtype, shape, device):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if t.is_conj() or t.is_neg():
+        # a lazy conjugate/negative view: its memory holds the unconjugated
+        # values, which the kernels would read as they are
+        raise ValueError(f"{name} is a lazy conjugate or negative view; pass "
+                         f"{name}.resolve_conj().resolve_neg()")
 
 
 def _prepare(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
@@ -108,9 +113,10 @@ def sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
-    st = lib.gpp_sigma_fwd(C.byref(dims), C.byref(ins), _ptr(ach), _ptr(asx),
-                           _ptr(workspace), workspace.numel(),
-                           C.c_void_p(stream))
+    with torch.cuda.device(dev):
+        st = lib.gpp_sigma_fwd(C.byref(dims), C.byref(ins), _ptr(ach), _ptr(asx),
+                               _ptr(workspace), workspace.numel(),
+                               C.c_void_p(stream))
     _lib.check(st, "gpp_sigma_fwd")
     return ach, asx
 
@@ -145,10 +151,11 @@ def sigma_bwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
     p = lambda t: _ptr(t) if t is not None else C.c_void_p(0)
-    st = lib.gpp_sigma_bwd(C.byref(dims), C.byref(ins), _ptr(grad_achtemp),
-                           _ptr(grad_asxtemp), p(outs[0]), p(outs[1]), p(outs[2]),
-                           p(outs[3]), _ptr(workspace), workspace.numel(),
-                           C.c_void_p(stream))
+    with torch.cuda.device(dev):
+        st = lib.gpp_sigma_bwd(C.byref(dims), C.byref(ins), _ptr(grad_achtemp),
+                               _ptr(grad_asxtemp), p(outs[0]), p(outs[1]), p(outs[2]),
+                               p(outs[3]), _ptr(workspace), workspace.numel(),
+                               C.c_void_p(stream))
     _lib.check(st, "gpp_sigma_bwd")
     return tuple(outs)
 
@@ -177,8 +184,9 @@ def _make_function():
             nw = ins[5].shape[0]
             dev = ins[0].device
             zero = lambda: torch.zeros(nw, dtype=torch.complex128, device=dev)
-            g_ach = zero() if g_ach is None else g_ach.contiguous()
-            g_asx = zero() if g_asx is None else g_asx.contiguous()
+            fix = lambda g: g.resolve_conj().resolve_neg().contiguous()
+            g_ach = zero() if g_ach is None else fix(g_ach)
+            g_asx = zero() if g_asx is None else fix(g_asx)
             want = tuple(bool(x) for x in ctx.needs_input_grad[:4])
             if not any(want):
                 return (None,) * 7
@@ -280,7 +288,8 @@ def sigma_batched(plan: Plan, states, *, out=None, workspace=None, stream=None):
                                 device=dev)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
-    st = lib.gpp_sigma_batched(plan._h, ins, _ptr(ach), _ptr(asx), _ptr(workspace),
-                               workspace.numel(), C.c_void_p(stream))
+    with torch.cuda.device(dev):
+        st = lib.gpp_sigma_batched(plan._h, ins, _ptr(ach), _ptr(asx), _ptr(workspace),
+                                   workspace.numel(), C.c_void_p(stream))
     _lib.check(st, "gpp_sigma_batched")
     return ach, asx

@@ -62,8 +62,9 @@ def ladder_fwd(step, aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_ar
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
-    st = lib.gpp_ladder_fwd(int(step), C.byref(dims), C.byref(ins), _ptr(ach), _ptr(asx),
-                            _ptr(workspace), workspace.numel(), C.c_void_p(stream))
+    with torch.cuda.device(dev):
+        st = lib.gpp_ladder_fwd(int(step), C.byref(dims), C.byref(ins), _ptr(ach), _ptr(asx),
+                                _ptr(workspace), workspace.numel(), C.c_void_p(stream))
     _lib.check(st, "gpp_ladder_fwd")
     return ach, asx
 

@@ -167,9 +167,10 @@ def test_tuning_cache_roundtrip_and_corruption(tmp_path):
     assert not (tmp_path / "other.json").exists()
 
 
-def test_batched_workload_subset_against_golden(gpp, tmp_path, monkeypatch):
-    """States of the 64-state batched workload at full size (the smallest,
-    the largest and a spread between) against oracle outputs written by
+def test_batched_workload_all_states_against_golden(gpp, tmp_path, monkeypatch):
+    """All 64 states of the batched workload at full size (about 53 GB of
+    inputs, drawn and uploaded state by state) in one plan -- the launch
+    configuration bench.py times -- against oracle outputs written by
     tests/golden/make_golden.py."""
     import torch
     path = os.path.join(ROOT, "tests", "golden", "fwd_batched.json")
@@ -177,19 +178,27 @@ def test_batched_workload_subset_against_golden(gpp, tmp_path, monkeypatch):
         pytest.skip("tests/golden/fwd_batched.json not generated")
     gold = json.load(open(path))["states"]
     dims = I.batched_dims()
-    size = lambda s: dims[s].ch_terms
-    have = sorted(int(s) for s in gold)
-    pick = sorted({min(have, key=size), max(have, key=size)} |
-                  set(have[:: max(1, len(have) // 5)]))[:7]
+    if sorted(int(s) for s in gold) != list(range(len(dims))):
+        pytest.skip("tests/golden/fwd_batched.json does not hold every state")
+    need = sum(16 * (2 * d.number_bands * d.ncouls + 2 * d.ngpown * d.ncouls)
+               + 8 * (d.ncouls + d.nfreq * d.number_bands) for d in dims)
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (8 << 30):
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} free")
     monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
-    say(f"[batched] golden subset states {pick}")
-    probs = dict(I.make_batched(states=pick))
-    plan = gpp.Plan([dims[s].as_tuple() for s in pick])
-    ach, asx = gpp.sigma_batched(plan, [to_device(probs[s]) for s in pick])
+    say(f"[batched] uploading all {len(dims)} states ({need / 2**30:.1f} GiB)")
+    dev = [to_device(prob) for _, prob in I.make_batched()]
+    plan = gpp.Plan([d.as_tuple() for d in dims])
+    ach, asx = gpp.sigma_batched(plan, dev)
     torch.cuda.synchronize()
     c = lambda pairs: np.array([complex(a, b) for a, b in pairs])
-    for k, s in enumerate(pick):
-        g = gold[str(s)]
-        assert_parity(ach[k].cpu().numpy(), c(g["achtemp"]), g["ach_abs_sum"], f"state {s}")
-        assert_parity(asx[k].cpu().numpy(), c(g["asxtemp"]), g["asx_abs_sum"], f"state {s}")
+    worst = 0.0
+    for k in range(len(dims)):
+        g = gold[str(k)]
+        worst = max(worst,
+                    assert_parity(ach[k].cpu().numpy(), c(g["achtemp"]), g["ach_abs_sum"], f"state {k}"),
+                    assert_parity(asx[k].cpu().numpy(), c(g["asxtemp"]), g["asx_abs_sum"], f"state {k}"))
+    say(f"[batched] all states max rel err {worst:.2e}, plan {plan.info()}")
     plan.close()
+    del dev
+    torch.cuda.empty_cache()

@@ -204,3 +204,35 @@ def test_autograd_gradcheck_tiny(gpp):
             ("aqsmtemp", "aqsntemp", "I_eps_array", "wtilde_array", "vcoul", "wx_array")]
     fn = lambda *a: gpp.sigma(*a, 1)
     assert torch.autograd.gradcheck(fn, args, eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_autograd_through_conjugated_and_negated_outputs(gpp):
+    """A loss written with torch.conj(...) of the outputs and a negation
+    hands backward lazily conjugated / negated gradient views; the
+    gradients must equal the direct call with the equivalent upstream
+    gradient (Re(g conj(z)) = Re(conj(g) z))."""
+    import torch
+    prob = I.make_problem(I.Dims(10, 2, 200, 5, 3), 12, 0.05)
+    d = to_device(prob)
+    leaves = {k: v.clone().requires_grad_(k in ARRAYS) for k, v in d.items()}
+    ach, asx = gpp.sigma(**leaves, nvband=2)
+    ga, gs = I.make_upstream_grad(3, np.random.default_rng(10))
+    gat = torch.from_numpy(ga).to("cuda:0")
+    gst = torch.from_numpy(gs).to("cuda:0")
+    L = torch.sum((gat * torch.conj(ach)).real) - torch.sum((-gst * torch.conj(asx)).real)
+    L.backward()
+    direct = gpu_grads(gpp, prob, ga, gs)
+    for name in ARRAYS:
+        assert np.array_equal(leaves[name].grad.cpu().numpy(), direct[name]), name
+
+
+def test_lazy_conjugate_inputs_are_rejected(gpp):
+    prob = I.make_problem(I.Dims(4, 1, 64, 2, 3), 3)
+    d = to_device(prob)
+    d["aqsntemp"] = d["aqsntemp"].conj()
+    with pytest.raises(ValueError, match="conjugate"):
+        gpp.sigma_fwd(**d, nvband=1)
+    d = to_device(prob)
+    d["wtilde_array"] = d["wtilde_array"].conj()
+    with pytest.raises(ValueError, match="conjugate"):
+        gpp.sigma(**d, nvband=1)

@@ -118,7 +118,7 @@ def test_bitwise_deterministic(gpp):
     assert np.array_equal(a1, a2) and np.array_equal(s1, s2)
 
 
-@pytest.mark.parametrize("key", ["adjoint", "si"])
+@pytest.mark.parametrize("key", ["adjoint", "si", "large"])
 def test_full_size_against_golden(gpp, key):
     """Full-size workloads in the launch configuration the benchmark times,
     against oracle outputs written by tests/golden/make_golden.py."""

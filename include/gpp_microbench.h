@@ -3,8 +3,8 @@
  * kernels' roofline (the measured-ceiling idea of the Empirical Roofline
  * Toolkit the paper cites in Sec. I).  Not part of the GPP computation.
  *
- * Both enqueue one kernel on `stream` (hipStream_t, NULL = default) and
- * return without synchronising; the caller times them with events.
+ * Each enqueues one kernel on `stream` (hipStream_t, NULL = default) and
+ * returns without synchronising; the caller times it with events.
  * Return 0 on success, 1 on invalid arguments, 2 on a HIP launch error.
  */
 #ifndef GPP_MICROBENCH_H
@@ -27,6 +27,19 @@ int gpp_mb_fp64_fma(double *out, int blocks, int iters, void *stream, double *fl
  * reads and writes exactly `bytes` each, the reference for scaling
  * FETCH_SIZE / WRITE_SIZE hardware counters. */
 int gpp_mb_copy(const void *src, void *dst, int64_t bytes, int blocks, void *stream);
+
+/* Read bandwidth of the level that holds the working set: `blocks`
+ * workgroups of 256 lanes each read a window of `window_bytes` (multiple of
+ * 16) `reps` times.  shared = 0: workgroup b reads bytes
+ * [b*window_bytes, (b+1)*window_bytes) of buf, so buf holds
+ * blocks*window_bytes; shared != 0: every workgroup reads the first
+ * window, from its own rotated start, so buf holds window_bytes.  Bytes
+ * read = blocks * window_bytes * reps.  out: device double [blocks * 256]
+ * (written, keeps the loads live).  A small per-workgroup window measures
+ * the vector L1, a shared window of a few MB the L2, one of tens of MB the
+ * MALL (Infinity Cache), and large per-workgroup windows HBM. */
+int gpp_mb_read(const void *buf, int64_t window_bytes, int shared, int blocks, int reps,
+                double *out, void *stream);
 
 #ifdef __cplusplus
 }

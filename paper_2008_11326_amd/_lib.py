@@ -81,6 +81,8 @@ _SIGNATURES = [
      [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
     ("gpp_mb_copy", C.c_int,
      [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
+    ("gpp_mb_read", C.c_int,
+     [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
 

@@ -1,6 +1,7 @@
 // gpp_microbench.hip -- empirical machine ceilings for the roofline: an
-// fp64 FMA issue-rate kernel and a streaming copy of known size (the
-// reference for scaling hardware byte counters).  Declared in
+// fp64 FMA issue-rate kernel, a streaming copy of known size (the
+// reference for scaling hardware byte counters) and a read-bandwidth
+// kernel whose window size selects the cache level it measures.  Declared in
 // include/gpp_microbench.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -37,6 +38,39 @@ __global__ void __launch_bounds__(256) mb_copy(const double2 *__restrict__ src,
         dst[i] = src[i];
 }
 
+// Read bandwidth of one level of the memory hierarchy.  Workgroup b reads a
+// window of `win` 16-byte elements `reps` times, 256 lanes x 16 B per step,
+// four loads in flight per lane.  shared = 0: window b of the buffer (its
+// own); shared = 1: the buffer's first window, every workgroup starting at
+// its own rotated offset (4096 elements apart) so that the workgroups on one
+// CU read different lines.  The sums keep the loads live.
+__global__ void __launch_bounds__(256) mb_read(const double2 *__restrict__ buf, long win,
+                                               int shared, int reps, double *out)
+{
+    const double2 *w = buf + (shared ? 0 : (size_t)blockIdx.x * win);
+    const long start = shared ? ((long)blockIdx.x * 4096) % win : 0;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < reps; ++r) {
+        long i = threadIdx.x;
+        for (; i + 3 * 256 < win; i += 4 * 256) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                long j = start + i + k * 256;
+                if (j >= win) j -= win;
+                const double2 v = w[j];
+                s[k] += v.x + v.y;
+            }
+        }
+        for (; i < win; i += 256) {
+            long j = start + i;
+            if (j >= win) j -= win;
+            const double2 v = w[j];
+            s[0] += v.x + v.y;
+        }
+    }
+    out[(size_t)blockIdx.x * 256 + threadIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -56,6 +90,18 @@ int gpp_mb_copy(const void *src, void *dst, int64_t bytes, int blocks, void *str
     if (((uintptr_t)src | (uintptr_t)dst) % 16) return 1;
     hipLaunchKernelGGL(mb_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                        (const double2 *)src, (double2 *)dst, (long)(bytes / 16));
+    return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
+int gpp_mb_read(const void *buf, int64_t window_bytes, int shared, int blocks, int reps,
+                double *out, void *stream)
+{
+    if (!buf || !out || window_bytes <= 0 || window_bytes % 16 || blocks <= 0 || reps <= 0)
+        return 1;
+    if ((uintptr_t)buf % 16) return 1;
+    hipLaunchKernelGGL(mb_read, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const double2 *)buf, (long)(window_bytes / 16), shared ? 1 : 0, reps,
+                       out);
     return hipGetLastError() == hipSuccess ? 0 : 2;
 }
 

@@ -1,5 +1,6 @@
-"""Empirical ceilings on this GPU: fp64 FMA rate and streaming-copy
-bandwidth (include/gpp_microbench.h).  Prints one JSON line.
+"""Empirical ceilings on this GPU: fp64 FMA rate, streaming-copy
+bandwidth and the read bandwidth of vL1D, L2, MALL and HBM
+(include/gpp_microbench.h).  Prints one JSON line.
 
     python -m paper_2008_11326_amd.microbench [--copy-mib 2048]
 
@@ -16,6 +17,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=2048)
     ap.add_argument("--fma-iters", type=int, default=4096)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--no-read-levels", dest="read_levels", action="store_false",
+                    help="skip the per-level read-bandwidth kernels")
     args = ap.parse_args()
 
     import torch
@@ -71,6 +74,31 @@ def main():
     res["copy_bytes_each_way"] = nbytes
     res["copy_ms"] = round(ms, 4)
     res["copy_gbps_read_plus_write"] = round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+
+    if args.read_levels:
+        # (shared, window bytes, workgroups per CU, reps) per level
+        levels = {
+            "vl1d": (0, 4 << 10, 4, 4096),    # 4 x 4 KiB per CU: inside the 32 KiB L1
+            "l2": (1, 2 << 20, 8, 8),         # one 2 MiB window: inside each XCD's L2
+            "mall": (1, 64 << 20, 8, 1),      # 64 MiB: beyond the L2s, inside the MALL
+            "hbm": (0, 2 << 20, 8, 2),        # 2 MiB per workgroup, 4 GiB in all
+        }
+        read = {}
+        for name, (shared, win, per_cu, reps) in levels.items():
+            blocks = cus * per_cu
+            nbuf = win if shared else win * blocks
+            buf = torch.ones(nbuf // 8, dtype=torch.float64, device=dev)
+            out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+
+            def rd():
+                _lib.check(lib.gpp_mb_read(C.c_void_p(buf.data_ptr()), win, shared, blocks,
+                                           reps, C.c_void_p(out.data_ptr()),
+                                           C.c_void_p(st.cuda_stream)), "gpp_mb_read")
+            ms = timed(rd)
+            read[name] = round(blocks * win * reps / (ms * 1e-3) / 1e12, 2)
+            del buf, out
+        res["read_tbps"] = read
     print(json.dumps(res), flush=True)
 
 

@@ -114,21 +114,28 @@ bool parse_cache(const std::string &t, std::map<std::string, TuneEntry> &out)
     return ch('}');
 }
 
-void load_cache_locked()
+// The entries of the cache file, or an empty map when it is missing or
+// does not parse (a corrupt cache is ignored).
+std::map<std::string, TuneEntry> read_cache_file(const std::string &path)
 {
-    if (g_cache_loaded) return;
-    g_cache_loaded = true;
-    const std::string path = cache_path();
-    if (path.empty()) return;
+    std::map<std::string, TuneEntry> parsed;
+    if (path.empty()) return parsed;
     FILE *f = fopen(path.c_str(), "rb");
-    if (!f) return;
+    if (!f) return parsed;
     std::string text;
     char buf[4096];
     size_t k;
     while ((k = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
     fclose(f);
-    std::map<std::string, TuneEntry> parsed;
-    if (parse_cache(text, parsed)) g_cache = parsed;  // else: ignore the corrupt file
+    if (!parse_cache(text, parsed)) parsed.clear();
+    return parsed;
+}
+
+void load_cache_locked()
+{
+    if (g_cache_loaded) return;
+    g_cache_loaded = true;
+    g_cache = read_cache_file(cache_path());
 }
 
 void mkdirs(const std::string &dir)
@@ -137,12 +144,15 @@ void mkdirs(const std::string &dir)
         if (pos == dir.size() || dir[pos] == '/') mkdir(dir.substr(0, pos).c_str(), 0755);
 }
 
-// Best effort: merge with what is on disk and replace the file atomically.
+// Best effort: merge with what is on disk now (other processes may have
+// added entries since this one read the file; this process's entries win)
+// and replace the file atomically.
 void store_cache_locked(const std::string &key, const TuneEntry &e)
 {
     g_cache[key] = e;
     const std::string path = cache_path();
     if (path.empty()) return;
+    for (const auto &kv : read_cache_file(path)) g_cache.insert(kv);  // keeps existing keys
     const size_t slash = path.rfind('/');
     if (slash != std::string::npos) mkdirs(path.substr(0, slash));
     const std::string tmp = path + ".tmp" + std::to_string((long)getpid());

@@ -32,14 +32,21 @@
  *          copy made by a transpose kernel inside the call
  *   8  v8  as 7, register cap of 80 VGPRs (6 waves per SIMD instead of
  *          the 5 its natural allocation gives; a few registers spill)
- *   9  the production forward (gpp_sigma_fwd)
+ *   9  m1  as 4, with the Coulomb-hole sum factored as in the production
+ *          kernel (om/(x - om) = r (x om - |om|^2): two running sums per
+ *          frequency, e and vcoul applied once per (G', G)), one reciprocal
+ *          per term
+ *  10  m2  as m1, with the denominators of 3 bands x nfreq frequencies
+ *          inverted together (one reciprocal per batch) and the branch mask
+ *          applied by clearing the high word
+ *  11  the production forward (gpp_sigma_fwd)
  *
  * The abs() predicates of steps 0-2 take moduli by square roots and compare
  * them multiplied out (A: |x - om| > 0.5 and |om| < 500 |x - om|; B:
  * |om| > 1e-6 |x - om|), so an exact pole needs no quotient.  They describe
  * the same regions as the exact predicate, but at an exact boundary
  * (|x - om|^2 == 0.25, or |om|^2 == 250000 |x - om|^2) rounding can put a
- * term on the other side.  Steps 0-8 support nfreq 1..4.
+ * term on the other side.  Steps 0-10 support nfreq 1..4.
  */
 #ifndef GPP_LADDER_H
 #define GPP_LADDER_H
@@ -50,7 +57,7 @@
 extern "C" {
 #endif
 
-#define GPP_LADDER_STEPS 10
+#define GPP_LADDER_STEPS 12
 #define GPP_LADDER_MAX_NFREQ 4
 
 /* Number of steps (GPP_LADDER_STEPS). */
@@ -67,7 +74,7 @@ size_t gpp_ladder_workspace(int32_t step, const gpp_dims *dims);
 /* The forward reduction of gpp_sigma_fwd computed by ladder step `step`.
  * Arguments, layouts, ownership and error behaviour as gpp_sigma_fwd; in
  * addition GPP_ERR_INVALID for a step outside [0, GPP_LADDER_STEPS) or, for
- * steps 0-8, nfreq > GPP_LADDER_MAX_NFREQ.  The workspace (16-byte aligned)
+ * steps 0-10, nfreq > GPP_LADDER_MAX_NFREQ.  The workspace (16-byte aligned)
  * must hold gpp_ladder_workspace(step, dims) bytes. */
 gpp_status gpp_ladder_fwd(int32_t step, const gpp_dims *dims, const gpp_inputs *inputs,
                           double *achtemp, double *asxtemp, void *workspace,

@@ -25,6 +25,9 @@
 //                (band-contiguous per G' column), made inside the call
 //   registers    v8: the kernel held to 80 VGPRs (6 waves per SIMD, one
 //                step above its natural 5, at the price of a few spills)
+// and then two steps toward the production kernel: m1 (v4's mapping with
+// the Coulomb-hole sum factored, lad_factored) and m2 (m1 with batch
+// inversion), before the production forward itself.
 // Each workgroup writes one partial row of 4*nfreq doubles; the forward's
 // fixed-order two-stage reduction adds them.  No atomics.
 #include <math.h>
@@ -247,6 +250,105 @@ lad_blocked_capped(int nb, int nv, int ng, int np, int w0, int nw, int npb, DevI
     lad_blocked_body<true>(nb, nv, ng, np, w0, nw, npb, in, amT, partials);
 }
 
+// m1 (BATCH = false) and m2 (BATCH = true): v4's mapping (thread <-> (p, g),
+// bands serial, every frequency in registers) with the production
+// forward's Coulomb-hole factoring: om/(x - om) = r (x om - |om|^2) with
+// r = 1/|x - om|^2, so each lane keeps P1 = sum r x Qm and P2 = sum r Qm
+// (Qm = aqsntemp conj(aqsmtemp) per band) and applies om, |om|^2, e and
+// vcoul once at the end.  Occupied bands take v4's exact per-term path.  m1
+// takes one reciprocal (rcp_nr2) per term; m2 batch-inverts the
+// denominators of 3 bands x NW frequencies and masks with the high-word
+// clear, as the production kernel does.
+template <int NW, bool BATCH>
+__global__ void __launch_bounds__(kLadThreads)
+lad_factored(int nb, int nv, int ng, int np, DevInputs in, double *__restrict__ partials)
+{
+    double acc[4 * NW];
+#pragma unroll
+    for (int j = 0; j < 4 * NW; ++j) acc[j] = 0.0;
+    const long f = (long)blockIdx.x * kLadThreads + threadIdx.x;
+    if (f < (long)np * ng) {
+        const int p = (int)(f / ng), g = (int)(f - (long)p * ng);
+        const cplx om = cload(in.wt + (size_t)p * ng + g);
+        const cplx ev = cscale(0.5 * in.vcoul[g], cload(in.ieps + (size_t)p * ng + g));
+        const double a = om.re, wi2 = om.im * om.im;
+        const double wtr = fma(a, a, wi2);
+        const double thr = branch_a_threshold(wtr);
+        for (int n = 0; n < nv; ++n) {
+            const cplx an = cload(in.aqsn + (size_t)n * ng + g);
+            const cplx am = cload(in.aqsm + (size_t)n * ng + p);
+            lad_terms<NW, Div::Rcp, Pred::Square, Br::Two>(cmul(cmul_conj(an, am), ev), om, true,
+                                                          in.wx + n, nb, 0, acc);
+        }
+        cplx P1[NW], P2[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) P1[w] = P2[w] = cmake(0.0, 0.0);
+        int n = nv;
+        if (BATCH) {
+            constexpr int K = 3 * NW;
+            const bool wide = wi2 >= kMinUnclampedWi2;
+            for (; n + 3 <= nb; n += 3) {
+                cplx qm[3];
+                double xs[K], dc[K], r[K];
+                bool isA[K];
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    qm[u] = cmul_conj(cload(in.aqsn + (size_t)(n + u) * ng + g),
+                                      cload(in.aqsm + (size_t)(n + u) * ng + p));
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) xs[u * NW + w] = in.wx[(size_t)w * nb + n + u];
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double dr = xs[k] - a;
+                    const double wd = fma(dr, dr, wi2);
+                    isA[k] = wd > thr;
+                    dc[k] = wd;
+                }
+                batch_reciprocal<K>(dc, r, wide);
+#pragma unroll
+                for (int u = 0; u < 3; ++u)
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        const int k = u * NW + w;
+                        const double re = mask_keep(isA[k], r[k]);
+                        const double rx = re * xs[k];
+                        P1[w].re = fma(rx, qm[u].re, P1[w].re);
+                        P1[w].im = fma(rx, qm[u].im, P1[w].im);
+                        P2[w].re = fma(re, qm[u].re, P2[w].re);
+                        P2[w].im = fma(re, qm[u].im, P2[w].im);
+                    }
+            }
+        }
+        for (; n < nb; ++n) {  // m1: every unoccupied band; m2: the ragged tail
+            const cplx qm = cmul_conj(cload(in.aqsn + (size_t)n * ng + g),
+                                      cload(in.aqsm + (size_t)n * ng + p));
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const double x = in.wx[(size_t)w * nb + n];
+                const double dr = x - a;
+                const double wd = fma(dr, dr, wi2);
+                const double r = wd > thr ? rcp_nr2(wd) : 0.0;
+                const double rx = r * x;
+                P1[w].re = fma(rx, qm.re, P1[w].re);
+                P1[w].im = fma(rx, qm.im, P1[w].im);
+                P2[w].re = fma(r, qm.re, P2[w].re);
+                P2[w].im = fma(r, qm.im, P2[w].im);
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            cplx S = cmul(om, P1[w]);
+            S.re = fma(-wtr, P2[w].re, S.re);
+            S.im = fma(-wtr, P2[w].im, S.im);
+            const cplx ch = cmul(ev, S);
+            acc[4 * w + 0] += ch.re;
+            acc[4 * w + 1] += ch.im;
+        }
+    }
+    lad_block_store<4 * NW>(acc, partials + (size_t)blockIdx.x * 4 * NW, 0);
+}
+
 // amT[p][n] = aqsmtemp[n][p] for p < np (one thread per element, writes
 // coalesced).
 __global__ void lad_transpose_am(int nb, int ng, int np, const double2 *__restrict__ aqsm,
@@ -268,6 +370,8 @@ const char *const kNames[GPP_LADDER_STEPS] = {
     "v6 as v5 with aqsntemp rows staged in LDS for 4 G' columns",
     "v7 as v6 with band-contiguous aqsmtemp (transposed copy)",
     "v8 as v7 with an 80-VGPR cap (6 waves per SIMD)",
+    "m1 v4 with the Coulomb-hole sum factored (P1/P2), one reciprocal per term",
+    "m2 as m1 with batch inversion over 3 bands and high-word masking",
     "production gpp_sigma_fwd",
 };
 
@@ -287,12 +391,12 @@ LadderGeometry ladder_geometry(int step, const Dims32 &d)
         if (step <= 3) {
             const long need = (total + kLadThreads - 1) / kLadThreads;
             geo.rows = need < kCollapseBlocks ? need : kCollapseBlocks;
-        } else if (step <= 5) {
+        } else if (step <= 5 || step >= 9) {
             geo.rows = ((long)d.np * d.ng + kLadThreads - 1) / kLadThreads;
         } else {
             geo.rows = (long)((d.ng + kWave - 1) / kWave) * ((d.np + kLadWaves - 1) / kLadWaves);
         }
-        if (step >= 7) geo.amT_bytes = up256((size_t)d.np * d.nb * sizeof(double2));
+        if (step == 7 || step == 8) geo.amT_bytes = up256((size_t)d.np * d.nb * sizeof(double2));
     }
     geo.partial_bytes = up256((size_t)geo.rows * 4 * d.nw * sizeof(double));
     geo.stage_bytes = up256(reduce_stage_bytes(d.nw, geo.rows));
@@ -364,6 +468,19 @@ hipError_t launch_ladder(int step, const Dims32 &d, const DevInputs &in, double2
         case 3: e = launch_bandinner_all<3>(d, geo, in, partials, st); break;
         default: e = launch_bandinner_all<4>(d, geo, in, partials, st); break;
         }
+    } else if (step == 9 || step == 10) {
+        const dim3 grid((unsigned)geo.rows), blk(kLadThreads);
+        switch (d.nw * 2 + (step == 10)) {
+        case 2: hipLaunchKernelGGL((lad_factored<1, false>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        case 3: hipLaunchKernelGGL((lad_factored<1, true>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        case 4: hipLaunchKernelGGL((lad_factored<2, false>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        case 5: hipLaunchKernelGGL((lad_factored<2, true>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        case 6: hipLaunchKernelGGL((lad_factored<3, false>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        case 7: hipLaunchKernelGGL((lad_factored<3, true>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        case 8: hipLaunchKernelGGL((lad_factored<4, false>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        default: hipLaunchKernelGGL((lad_factored<4, true>), grid, blk, 0, st, d.nb, d.nv, d.ng, d.np, in, partials); break;
+        }
+        e = hipGetLastError();
     } else if (step == 5) {
         for (int w = 0; w < d.nw && e == hipSuccess; ++w) {
             hipLaunchKernelGGL((lad_bandinner<1, Div::Rcp, Pred::Square, Br::Two>),
@@ -433,8 +550,8 @@ gpp_status gpp_ladder_fwd(int32_t step, const gpp_dims *dims, const gpp_inputs *
     gpp_status s;
     if ((s = gpp::check_dims(dims, &d))) return s;
     if (d.nw > GPP_LADDER_MAX_NFREQ)
-        return gpp::fail(GPP_ERR_INVALID, "ladder steps 0-8 take nfreq <= %d, got %d",
-                         GPP_LADDER_MAX_NFREQ, d.nw);
+        return gpp::fail(GPP_ERR_INVALID, "ladder steps 0-%d take nfreq <= %d, got %d",
+                         GPP_LADDER_STEPS - 2, GPP_LADDER_MAX_NFREQ, d.nw);
     if ((s = gpp::check_inputs(d, inputs, &din))) return s;
     if ((s = gpp::check_array("achtemp", achtemp, d.nw, 16)) ||
         (s = gpp::check_array("asxtemp", asxtemp, d.nw, 16)))

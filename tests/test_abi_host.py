@@ -188,24 +188,25 @@ def _ladder_call(lib, step, dims, ins=None, ws_bytes=None, ws=FAKE + 0x700000):
 
 def test_ladder_names_and_validation(lib):
     n = lib.gpp_ladder_steps()
-    assert n == 10
+    assert n == 12
     names = [lib.gpp_ladder_name(s).decode() for s in range(n)]
     assert [s[:2] for s in names[:9]] == [f"v{k}" for k in range(9)]
-    assert "production" in names[9]
+    assert [s[:2] for s in names[9:11]] == ["m1", "m2"]
+    assert "production" in names[n - 1]
     assert lib.gpp_ladder_name(-1) is None and lib.gpp_ladder_name(n) is None
     d = _dims()
     for bad in (-1, n):
         assert lib.gpp_ladder_workspace(bad, C.byref(d)) == 0
         assert _ladder_call(lib, bad, d, ws_bytes=256) == 1
         assert "step" in lib.gpp_last_error().decode()
-    # steps 0-8 take nfreq <= 4; the production step takes up to 8
+    # steps 0-10 take nfreq <= 4; the production step takes up to 8
     d5 = _dims(nw=5)
-    for step in range(9):
+    for step in range(n - 1):
         assert lib.gpp_ladder_workspace(step, C.byref(d5)) == 0
         assert _ladder_call(lib, step, d5, ws_bytes=1 << 20) == 1
         assert "nfreq" in lib.gpp_last_error().decode()
-    assert lib.gpp_ladder_workspace(9, C.byref(d5)) == lib.gpp_sigma_fwd_workspace(C.byref(d5))
-    for step in range(9):
+    assert lib.gpp_ladder_workspace(n - 1, C.byref(d5)) == lib.gpp_sigma_fwd_workspace(C.byref(d5))
+    for step in range(n - 1):
         assert lib.gpp_ladder_workspace(step, C.byref(d)) > 0
         assert _ladder_call(lib, step, d, ins=_inputs(aqsntemp=0)) == 1
         assert _ladder_call(lib, step, d, ws=0) == 4

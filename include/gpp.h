@@ -169,7 +169,7 @@ typedef struct {
     int32_t candidates;       /* size of the search space                    */
     int32_t schedule;         /* 0 = global round-robin, 1 = one contiguous
                                  chunk of the tile list per XCD, 2 = work
-                                 queue of 4-tile chunks, 3 = one such queue
+                                 queue of 2-tile chunks, 3 = one such queue
                                  per XCD (own region first, then stealing)   */
     int64_t total_tiles;      /* 64-row wave tiles over all states           */
     double tuned_ms;          /* measured time of the chosen candidate       */

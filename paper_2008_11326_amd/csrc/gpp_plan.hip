@@ -42,7 +42,13 @@ struct Candidate {
 
 // Tiles per work-queue chunk: small enough that the chunks in flight stay a
 // contiguous window of the tile list and the last chunks balance the end.
-constexpr int kQueueChunkTiles = 4;
+// The window is (resident waves) x (chunk tiles) consecutive G' columns, and
+// each column brings its own aqsmtemp column into L2: 2 keeps it near one
+// XCD's L2 at 512 bands (4 measured about 1 % slower, 1 no faster).
+#ifndef GPP_QUEUE_CHUNK_TILES
+#define GPP_QUEUE_CHUNK_TILES 2
+#endif
+constexpr int kQueueChunkTiles = GPP_QUEUE_CHUNK_TILES;
 // Workspace layout: [0, 256) the queue counters, then the partial rows.
 constexpr size_t kPartialsOffset = 256;
 

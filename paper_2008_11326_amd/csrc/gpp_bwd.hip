@@ -20,7 +20,9 @@
 //
 // Kernels: bwd_pairs (lane = g, wave-uniform p, bands serial) writes
 // dwtilde and dI_eps and, per workgroup of 256 rows, partial sums of
-// daqsmtemp.  The per-lane daqsmtemp terms of kSlab bands are parked in a
+// daqsmtemp.  Slabs of unoccupied bands form K and L from four factored
+// sums per band (see the slab loop); occupied bands and ragged slabs form
+// u and u^2 per term.  The per-lane daqsmtemp terms of kSlab bands are parked in a
 // per-wave LDS slab and summed together (8 lanes per band, then a DPP sum
 // over the 8), instead of one 64-lane shuffle reduction per band.
 // bwd_bands (lane = g, a wave owns kBandTile bands and walks every p)
@@ -40,12 +42,13 @@ constexpr int kChunk = 48;                         // bands per LDS flush (multi
 constexpr int kSlab = 6;                           // bands per in-wave transpose (two groups)
 constexpr int kOctet = 8;                          // lanes that share one band's row sum
 // Minimum waves per SIMD the compiler must allow (register cap) for the
-// pairs and bands kernels; 1 leaves the allocation to the compiler.  The
-// defaults (pairs 4 waves = 128 VGPRs with a few spills outside the band
-// loop, bands 5 waves = 96 VGPRs) each measured about 1.3 % faster on the
-// nb256/ng16384/np819 adjoint workload than the compiler's own choice.
+// pairs and bands kernels; 1 leaves the allocation to the compiler.  Pairs:
+// 3 waves (up to 168 VGPRs; the factored slab loop needs about 160, and a
+// 4-wave cap spills it, 5-6 % slower on the nb256/ng16384/np819 adjoint
+// workload).  Bands: 5 waves = 96 VGPRs, about 1.3 % faster there than the
+// compiler's own choice.
 #ifndef GPP_BWD_PAIRS_WAVES
-#define GPP_BWD_PAIRS_WAVES 4
+#define GPP_BWD_PAIRS_WAVES 3
 #endif
 #ifndef GPP_BWD_BANDS_WAVES
 #define GPP_BWD_BANDS_WAVES 5
@@ -175,8 +178,34 @@ __device__ __forceinline__ void sx_band_kl(int n, int nb, const double *__restri
     }
 }
 
+// Batch-inverted reciprocals of the BU*NW terms of BU bands starting at
+// band n for one lane, masked to branch A, and dr = x - Re om.
+template <int NW, int BU>
+__device__ __forceinline__ void group_reciprocals(int n, int nb, const double *__restrict__ wx,
+                                                  double a, double wi2, double thr, bool wide,
+                                                  double (&r)[BU * NW], double (&drs)[BU * NW])
+{
+    constexpr int Kt = BU * NW;
+    double dc[Kt];
+    bool isA[Kt];
+#pragma unroll
+    for (int u = 0; u < BU; ++u)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) drs[u * NW + w] = wx[(size_t)w * nb + n + u] - a;
+#pragma unroll
+    for (int k = 0; k < Kt; ++k) {
+        const double wd = fma(drs[k], drs[k], wi2);
+        isA[k] = wd > thr;
+        dc[k] = wd;  // unclamped: see batch_reciprocal
+    }
+    batch_reciprocal<Kt>(dc, r, wide);
+#pragma unroll
+    for (int k = 0; k < Kt; ++k) r[k] = mask_keep(isA[k], r[k]);
+}
+
 struct PairState {
     double a, b, wi2, wtr, thr;
+    double b2, wi2x2;  // 2 Im om and 2 (Im om)^2
     bool wide;  // (Im om)^2 >= kMinUnclampedWi2: batch inversion allowed
     cplx om, e, ve;  // ve = vcoul[g] e (0 for rows beyond ncouls)
 };
@@ -191,6 +220,8 @@ __device__ __forceinline__ PairState load_pair(const double2 *wt, const double2 
     s.a = s.om.re;
     s.b = s.om.im;
     s.wi2 = s.b * s.b;
+    s.b2 = 2.0 * s.b;
+    s.wi2x2 = 2.0 * s.wi2;
     s.wtr = fma(s.a, s.a, s.wi2);
     s.thr = branch_a_threshold(s.wtr);
     s.wide = s.wi2 >= kMinUnclampedWi2;
@@ -238,6 +269,62 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
         for (int b0 = c0; b0 < c1; b0 += kSlab) {
             const int b1 = b0 + kSlab < c1 ? b0 + kSlab : c1;
             int n = b0;
+            if (b0 >= nv && b1 - b0 == kSlab) {
+                // A whole slab of unoccupied bands: no exchange terms, whole
+                // groups, and K, L from factored sums.  With r_w the masked
+                // reciprocal of |x_w - om|^2 and dr_w = x_w - Re om, every
+                // branch-A term has |x_w - om|^2 r_w = 1, so
+                //   u_w^2 = r_w - 2 (Im om)^2 r_w^2 - 2i (Im om) dr_w r_w^2,
+                //   K = S - om R,  L = S - 2 (Im om)^2 T - 2i (Im om) U,
+                //   S = sum_w xgh_w r_w,  R = sum_w gh_w r_w,
+                //   T = sum_w xgh_w r_w^2,  U = sum_w xgh_w dr_w r_w^2:
+                // four complex-by-real multiply-adds per term.
+#pragma unroll 1
+                for (int q0 = 0; q0 < kSlab; q0 += kBwdGroup) {
+                    constexpr int Kt = kBwdGroup * NW;
+                    double r[Kt], drs[Kt];
+                    const int ng0 = opaque_uniform(__builtin_amdgcn_readfirstlane(b0 + q0));
+                    group_reciprocals<NW, kBwdGroup>(ng0, nb, wx, ps.a, ps.wi2, ps.thr,
+                                                     ps.wide, r, drs);
+#pragma unroll
+                    for (int u = 0; u < kBwdGroup; ++u) {
+                        const int nn = ng0 + u;
+                        cplx S = cmake(0.0, 0.0), R = S, T = S, U = S;
+#pragma unroll
+                        for (int w = 0; w < NW; ++w) {
+                            const int k = u * NW + w;
+                            const double q = r[k] * r[k];
+                            const double dq = drs[k] * q;
+                            const cplx g = cload(gh + w);
+                            const cplx xg = cload(xgh + (size_t)w * nb + nn);
+                            S.re = fma(r[k], xg.re, S.re);
+                            S.im = fma(r[k], xg.im, S.im);
+                            R.re = fma(r[k], g.re, R.re);
+                            R.im = fma(r[k], g.im, R.im);
+                            T.re = fma(q, xg.re, T.re);
+                            T.im = fma(q, xg.im, T.im);
+                            U.re = fma(dq, xg.re, U.re);
+                            U.im = fma(dq, xg.im, U.im);
+                        }
+                        // Z = conj(om) (S - om R),  W = L
+                        const cplx Z = cmake(fma(ps.a, S.re, fma(ps.b, S.im, -ps.wtr * R.re)),
+                                             fma(ps.a, S.im, fma(-ps.b, S.re, -ps.wtr * R.im)));
+                        const cplx W = cmake(fma(ps.b2, U.im, fma(-ps.wi2x2, T.re, S.re)),
+                                             fma(-ps.b2, U.re, fma(-ps.wi2x2, T.im, S.im)));
+                        const cplx an = load_row_elem(as_global(aqsn) + (size_t)nn * ng, ng, goff);
+                        const cplx am = cload(am_col + (size_t)nn * ng);
+                        const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
+                        cmac(Ge, cM, Z);
+                        cmac(Gw, cM, W);
+                        if (am_part) {
+                            const cplx t = cmul(ps.ve, cmul_conj(an, Z));
+                            slab[wid][nn - b0][lane] = make_double2(t.re, t.im);
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                n = b1;
+            }
             while (n < b1) {
                 // bands n .. n+cnt-1 form one batch-inverted group
                 const bool occ = n < nv;

@@ -109,7 +109,10 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
 
 /* Bytes of device workspace gpp_sigma_bwd needs for `dims` (host-only
  * computation).  It grows as ceil(ncouls/256) * number_bands * ngpown * 16
- * bytes (partial sums of the aqsmtemp gradient).  Returns 0 for invalid
+ * bytes (partial sums of the aqsmtemp gradient), plus, for problems small
+ * enough that the aqsntemp-gradient pass splits its G' range into S > 1
+ * segments to fill the GPU, S * number_bands * ncouls * 16 bytes (S <= 16
+ * when ngpown >= 1024; 4 at 256 bands x 16384 rows).  Returns 0 for invalid
  * dims. */
 size_t gpp_sigma_bwd_workspace(const gpp_dims *dims);
 

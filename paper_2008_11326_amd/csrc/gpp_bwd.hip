@@ -57,6 +57,15 @@ constexpr int kOctet = 8;                          // lanes that share one band'
 #define GPP_BWD_BAND_TILE 3
 #endif
 constexpr int kBandTile = GPP_BWD_BAND_TILE;       // bands per bands-kernel wave
+// Bands-kernel p-range split (see bwd_geometry): resident bands waves of the
+// MI355X (256 CUs x 4 SIMDs x GPP_BWD_BANDS_WAVES), rounds of them to aim
+// at, and the shortest segment.
+#ifndef GPP_BWD_BANDS_ROUNDS
+#define GPP_BWD_BANDS_ROUNDS 16
+#endif
+constexpr long kBandsWaveSlots = 256L * 4 * GPP_BWD_BANDS_WAVES;
+constexpr int kBandsRounds = GPP_BWD_BANDS_ROUNDS;
+constexpr int kMinSegCols = 64;
 static_assert(kBandTile % kBwdGroup == 0, "band tile must be whole groups");
 
 // Upstream gradient scaled for the kernels: gh[w] = ga[w]/2 and
@@ -424,7 +433,8 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
 // so vcoul conj(e) Z = vcoul conj(e) conj(om) K = c1 S - c2 R with the
 // per-pair constants c1 = vcoul conj(e om) and c2 = vcoul conj(e) |om|^2.
 template <int NW>
-__device__ __forceinline__ void bands_fast(int nb, int ng, int np, int n0, int gc, double vc,
+__device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, int n0, int gc,
+                                           double vc,
                                            gptr<double2> aqsm, gptr<double2> ieps,
                                            gptr<double2> wt, gptr<double> wx,
                                            gptr<double2> gh, gptr<double2> xgh,
@@ -433,11 +443,11 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int np, int n0, int g
     constexpr int Kt = kBwdGroup * NW;
     // om and e of the next column are loaded one iteration ahead, so their
     // latency overlaps this column's arithmetic
-    cplx om_next = cload(wt + gc), e_next = cload(ieps + gc);
-    for (int p = 0; p < np; ++p) {
+    cplx om_next = cload(wt + (size_t)p_lo * ng + gc), e_next = cload(ieps + (size_t)p_lo * ng + gc);
+    for (int p = p_lo; p < p_hi; ++p) {
         const int nfirst = opaque_uniform(n0);  // reload x and xgh per p
         const cplx om = om_next, e = e_next;
-        const int pn = p + 1 < np ? p + 1 : p;
+        const int pn = p + 1 < p_hi ? p + 1 : p;
         om_next = cload(wt + (size_t)pn * ng + gc);
         e_next = cload(ieps + (size_t)pn * ng + gc);
         const double a = om.re, b = om.im;
@@ -492,7 +502,8 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int np, int n0, int g
 
 // Generic form: occupied bands (exchange terms) and a ragged last tile.
 template <int NW>
-__device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int np, int n0, int gc,
+__device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int p_lo, int p_hi, int n0,
+                                              int gc,
                                               bool valid, const double2 *__restrict__ aqsm,
                                               const double2 *__restrict__ ieps,
                                               const double2 *__restrict__ wt,
@@ -502,7 +513,7 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int np, in
                                               const double2 *__restrict__ gs,
                                               cplx (&acc)[kBandTile])
 {
-    for (int p = 0; p < np; ++p) {
+    for (int p = p_lo; p < p_hi; ++p) {
         const PairState ps = load_pair(wt, ieps, vcoul, p, ng, gc, valid);
         const cplx vce = cmake(ps.ve.re, -ps.ve.im);           // vcoul conj(e)
         const cplx vcw = cmul(vce, cmake(ps.om.re, -ps.om.im));  // vcoul conj(e om)
@@ -549,7 +560,7 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int np, in
 template <int NW>
 __global__ void __launch_bounds__(kBwdThreads)
 __attribute__((amdgpu_waves_per_eu(GPP_BWD_BANDS_WAVES)))
-bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
+bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt, int ngt, int nps,
           const double2 *__restrict__ aqsm, const double2 *__restrict__ ieps,
           const double2 *__restrict__ wt, const double *__restrict__ vcoul,
           const double *__restrict__ wx, const double2 *__restrict__ gh,
@@ -560,9 +571,16 @@ bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const long tile = (long)xcd_remap(blockIdx.x, gridDim.x) * kBwdWaves + wid;
     if (tile >= ntiles) return;  // wave-uniform; no barriers below
-    // band tile fastest: neighbouring waves share the g rows of wtilde/I_eps
-    const int gt = (int)(tile / nbt);
-    const int n0 = (int)(tile - (long)gt * nbt) * kBandTile;
+    // band tile fastest (neighbouring waves share the g rows of wtilde/I_eps),
+    // then g tile, then segment of the p range
+    const long per_seg = (long)ngt * nbt;
+    const int seg = (int)(tile / per_seg);
+    const long in_seg = tile - (long)seg * per_seg;
+    const int gt = (int)(in_seg / nbt);
+    const int n0 = (int)(in_seg - (long)gt * nbt) * kBandTile;
+    const int p_lo = (int)((long)np * seg / nps), p_hi = (int)((long)np * (seg + 1) / nps);
+    // one segment writes the gradient itself, several write partial sums
+    double2 *const dst = grad_an + (size_t)seg * nb * ng;
     const int g = gt * kWave + lane;
     const bool valid = g < ng;
     const int gc = valid ? g : ng - 1;
@@ -571,16 +589,17 @@ bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt,
 #pragma unroll
     for (int u = 0; u < kBandTile; ++u) acc[u] = cmake(0.0, 0.0);
     if (n0 >= nv && n0 + kBandTile <= nb)
-        bands_fast<NW>(nb, ng, np, n0, gc, valid ? vcoul[gc] : 0.0, as_global(aqsm),
+        bands_fast<NW>(nb, ng, p_lo, p_hi, n0, gc, valid ? vcoul[gc] : 0.0, as_global(aqsm),
                        as_global(ieps), as_global(wt), as_global(wx), as_global(gh),
                        as_global(xgh), acc);
     else
-        bands_generic<NW>(nb, nv, ng, np, n0, gc, valid, aqsm, ieps, wt, vcoul, wx, gh, gs, acc);
+        bands_generic<NW>(nb, nv, ng, p_lo, p_hi, n0, gc, valid, aqsm, ieps, wt, vcoul, wx, gh,
+                          gs, acc);
     if (valid) {
 #pragma unroll
         for (int u = 0; u < kBandTile; ++u) {
             const int n = n0 + u;
-            if (n < nb) grad_an[(size_t)n * ng + g] = make_double2(acc[u].re, acc[u].im);
+            if (n < nb) dst[(size_t)n * ng + g] = make_double2(acc[u].re, acc[u].im);
         }
     }
 }
@@ -604,6 +623,21 @@ __global__ void reduce_am(int nb, int ng, int np, int ngb, const double2 *__rest
     grad_am[i] = make_double2(re, im);
 }
 
+// daqsntemp = sum of the nps segment partials, in segment order.
+__global__ void reduce_an(long nbg, int nps, const double2 *__restrict__ part,
+                          double2 *__restrict__ grad_an)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbg) return;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < nps; ++s) {
+        const double2 v = part[(size_t)s * nbg + i];
+        re += v.x;
+        im += v.y;
+    }
+    grad_an[i] = make_double2(re, im);
+}
+
 __global__ void fill_zero_n(double2 *a, long n)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -619,13 +653,26 @@ BwdGeometry bwd_geometry(const Dims32 &d)
         geo.ngb = (d.ng + kRowsPerBlock - 1) / kRowsPerBlock;
         geo.pair_blocks = (long)geo.ngb * d.np;
         geo.nbt = (d.nb + kBandTile - 1) / kBandTile;
-        geo.band_tiles = (long)((d.ng + kWave - 1) / kWave) * geo.nbt;
+        geo.ngt = (d.ng + kWave - 1) / kWave;
+        // Split the p loop into segments when one pass has too few waves:
+        // every wave walks its whole p range, so the last partial round of
+        // a short grid leaves most SIMDs idle.  Aim at kBandsRounds rounds
+        // of the MI355X's resident bands waves, each segment at least
+        // kMinSegCols columns long.
+        const long per_seg = (long)geo.ngt * geo.nbt;
+        const long want = (long)kBandsRounds * kBandsWaveSlots;
+        long nps = (want + per_seg - 1) / per_seg;
+        const long max_nps = d.np / kMinSegCols > 1 ? d.np / kMinSegCols : 1;
+        geo.nps = (int)(nps < max_nps ? nps : max_nps);
+        geo.band_tiles = per_seg * geo.nps;
         geo.band_blocks = (geo.band_tiles + kBwdWaves - 1) / kBwdWaves;
         geo.am_part_elems = (size_t)geo.ngb * d.nb * d.np;
+        geo.an_part_elems = geo.nps > 1 ? (size_t)geo.nps * d.nb * d.ng : 0;
     }
     // complex elements, each 16 bytes; sections 256-byte aligned
     auto up = [](size_t e) { return (e * sizeof(double2) + 255) / 256 * 256; };
-    geo.workspace_bytes = up(geo.gh_elems) + up(geo.xgh_elems) + up(geo.am_part_elems);
+    geo.workspace_bytes = up(geo.gh_elems) + up(geo.xgh_elems) + up(geo.am_part_elems) +
+                          up(geo.an_part_elems);
     if (geo.workspace_bytes == 0) geo.workspace_bytes = 256;
     return geo;
 }
@@ -639,6 +686,8 @@ static hipError_t launch_bwd_nw(const Dims32 &d, const BwdGeometry &geo, const D
     double2 *gh = reinterpret_cast<double2 *>(ws);
     double2 *xgh = reinterpret_cast<double2 *>(ws + up(geo.gh_elems));
     double2 *am_part = reinterpret_cast<double2 *>(ws + up(geo.gh_elems) + up(geo.xgh_elems));
+    double2 *an_part = reinterpret_cast<double2 *>(ws + up(geo.gh_elems) + up(geo.xgh_elems) +
+                                                   up(geo.am_part_elems));
     const int prep = d.nw * d.nb > d.nw ? d.nw * d.nb : d.nw;
     hipLaunchKernelGGL(bwd_prepare, dim3((prep + 255) / 256), dim3(256), 0, st, d.nb, d.nw,
                        in.wx, ga, gh, xgh);
@@ -659,10 +708,17 @@ static hipError_t launch_bwd_nw(const Dims32 &d, const BwdGeometry &geo, const D
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (out.grad_an) {
+        double2 *an_dst = geo.nps > 1 ? an_part : out.grad_an;
         hipLaunchKernelGGL(bwd_bands<NW>, dim3((unsigned)geo.band_blocks), dim3(kBwdThreads), 0,
-                           st, d.nb, d.nv, d.ng, d.np, geo.band_tiles, geo.nbt, in.aqsm, in.ieps,
-                           in.wt, in.vcoul, in.wx, gh, xgh, gs, out.grad_an);
+                           st, d.nb, d.nv, d.ng, d.np, geo.band_tiles, geo.nbt, geo.ngt, geo.nps,
+                           in.aqsm, in.ieps, in.wt, in.vcoul, in.wx, gh, xgh, gs, an_dst);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (geo.nps > 1) {
+            const long nbg = (long)d.nb * d.ng;
+            hipLaunchKernelGGL(reduce_an, dim3((unsigned)((nbg + 255) / 256)), dim3(256), 0, st,
+                               nbg, geo.nps, an_part, out.grad_an);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }

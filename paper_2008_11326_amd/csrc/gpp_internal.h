@@ -31,9 +31,12 @@ struct BwdGeometry {
     int ngb = 0;             // 256-row blocks of the pairs kernel
     long pair_blocks = 0;    // pairs-kernel workgroups (ngb x np)
     int nbt = 0;             // band tiles of the bands kernel
-    long band_tiles = 0;     // bands-kernel waves (g tiles x band tiles)
+    int ngt = 0;             // 64-row g tiles of the bands kernel
+    int nps = 1;             // segments of the bands kernel's p range
+    long band_tiles = 0;     // bands-kernel waves (segments x g tiles x band tiles)
     long band_blocks = 0;
     size_t gh_elems = 0, xgh_elems = 0, am_part_elems = 0;  // complex elements
+    size_t an_part_elems = 0;  // per-segment daqsntemp partials (nps > 1 only)
     size_t workspace_bytes = 0;
 };
 

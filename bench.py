@@ -284,7 +284,7 @@ def main():
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": measured_traffic(wl.name),
-                     "kernel": "gpp::fwd_tiles<3,3> + two reduce_rows<3> (one gpp_sigma_fwd)",
+                     "kernel": "gpp::fwd_tiles<3,2> + two reduce_rows<3> (one gpp_sigma_fwd)",
                      "launch_ms": round(launch_ms, 4)},
     }
     res = (ach.cpu().numpy(), asx.cpu().numpy())

@@ -1,8 +1,8 @@
 // gpp_batched.hip -- persistent forward over many quasiparticle states of
 // uneven sizes in one launch (gfx950, fp64).
 //
-// The tiles of all states (each state's forward tiles: one G' column x 64
-// G rows, G'-column fastest) are concatenated in a schedule order chosen by
+// The tiles of all states (each state's forward tiles: one or two G'
+// columns x 64 G rows, G'-column fastest) are concatenated in a schedule order chosen by
 // the plan.  Two kernel forms exist: the static one below and a work-queue
 // one (batched_queue) whose waves take small chunks of the list from atomic
 // counters.  In the static form, persistent wave w takes global tiles
@@ -48,11 +48,34 @@ __device__ __forceinline__ void flush_state(const StateDesc *__restrict__ st, in
     for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
 }
 
-// Up to three frequencies the kernel is held to 128 VGPRs (4 waves per
-// SIMD); more frequencies need the larger register file per wave.
+// The forward work of one tile of state d (its local tile index), as in
+// the plain forward: one or two G' columns x 64 G rows.
+template <int NW, int BU>
+__device__ __forceinline__ void state_tile(const StateDesc &d, long local, int lane,
+                                           cplx (&a)[NW], cplx (&x)[NW])
+{
+    constexpr int C = bat_cols(NW);
+    const int npt = (d.np + C - 1) / C;
+    const int gt = (int)(local / npt);
+    const int pt = (int)(local - (long)gt * npt);
+    if (C == 1) {
+        fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, pt, gt, lane, as_global(d.aqsm),
+                              as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
+                              as_global(d.vcoul), as_global(d.wx), a, x);
+    } else {
+        const int p0 = 2 * pt;
+        const bool has1 = p0 + 1 < d.np;
+        fwd_tile_body_c2<NW, BU>(d.nb, d.nv, d.ng, p0, has1 ? p0 + 1 : p0, has1, gt, lane,
+                                 as_global(d.aqsm), as_global(d.aqsn), as_global(d.ieps),
+                                 as_global(d.wt), as_global(d.vcoul), as_global(d.wx), a, x);
+    }
+}
+
+// Register caps: two-column tiles (up to three frequencies) at 3 waves per
+// SIMD, one-column tiles with four or more frequencies uncapped.
 template <int NW, int BU>
 __global__ void __launch_bounds__(kBatThreads)
-__attribute__((amdgpu_waves_per_eu(NW <= 3 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(bat_cols(NW) == 2 ? GPP_BAT_WAVES2 : (NW <= 3 ? 4 : 1))))
 batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_tiles, int nwaves,
                    double *__restrict__ partials, const long *__restrict__ xcd_chunks)
 {
@@ -89,13 +112,8 @@ batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_til
             ++s;
         }
         const StateDesc d = st[s];
-        const long local = t - d.tile_begin;
-        const int gt = (int)(local / d.np);
-        const int p = (int)(local - (long)gt * d.np);
         cplx a[NW], x[NW];
-        fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, p, gt, lane, as_global(d.aqsm),
-                              as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
-                              as_global(d.vcoul), as_global(d.wx), a, x);
+        state_tile<NW, BU>(d, t - d.tile_begin, lane, a, x);
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             ach[w].re = to_uniform(ach[w].re + wave_sum(a[w].re));
@@ -121,7 +139,7 @@ batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_til
 // failed takes and every wave reaches the exit.
 template <int NW, int BU>
 __global__ void __launch_bounds__(kBatThreads)
-__attribute__((amdgpu_waves_per_eu(NW <= 3 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(bat_cols(NW) == 2 ? GPP_BAT_WAVES2 : (NW <= 3 ? 4 : 1))))
 batched_queue(const StateDesc *__restrict__ st, long nchunks, int chunk_tiles,
               unsigned long long *__restrict__ counter, const long *__restrict__ queue_begin,
               double *__restrict__ partials)
@@ -155,13 +173,8 @@ batched_queue(const StateDesc *__restrict__ st, long nchunks, int chunk_tiles,
 #pragma unroll
         for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
         for (long t = t0; t < t1; ++t) {
-            const long local = t - d.tile_begin;
-            const int gt = (int)(local / d.np);
-            const int p = (int)(local - (long)gt * d.np);
             cplx a[NW], x[NW];
-            fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, p, gt, lane, as_global(d.aqsm),
-                                  as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
-                                  as_global(d.vcoul), as_global(d.wx), a, x);
+            state_tile<NW, BU>(d, t - d.tile_begin, lane, a, x);
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 ach[w].re = to_uniform(ach[w].re + wave_sum(a[w].re));

@@ -1,12 +1,13 @@
 // gpp_fwd.hip -- forward GPP reduction on gfx950 (fp64 vector ALU, no MFMA).
 //
-// Work decomposition.  A wave owns one G' column p and 64 consecutive G
-// rows g (one per lane) and walks every band n sequentially, as in the
-// band-inner loop order of Sec. III v4 (bands serial per thread keeps the
-// g-fastest arrays coalesced and reads wtilde/I_eps once).  Within a wave
-// p and n are uniform, so aqsmtemp[n][p] and wx_array[w][n] are scalar
-// loads; the frequencies are register-blocked (all NW in one pass, none of
-// v5's recompute).
+// Work decomposition.  A wave owns two G' columns (one with more than three
+// frequencies) and 64 consecutive G rows g (one per lane) and walks every
+// band n sequentially, as in the band-inner loop order of Sec. III v4
+// (bands serial per thread keeps the g-fastest arrays coalesced and reads
+// wtilde/I_eps once); each aqsntemp[n][g] a lane loads serves both
+// columns.  Within a wave p and n are uniform, so aqsmtemp[n][p] and
+// wx_array[w][n] are scalar loads; the frequencies are register-blocked
+// (all NW in one pass, none of v5's recompute).
 //
 // Per lane, e = I_eps[p][g] and vcoul[g] are constant over the band loop,
 // so they multiply once at the end.  For a branch-A term,
@@ -17,9 +18,9 @@
 // test is one compare against a per-(p,g) threshold that reproduces the
 // specification exactly (gpp_device.h).  r = 1/wdiffr needs no IEEE divide
 // (the v1 idea); the BU*NW reciprocals of a group of BU bands come from a
-// single hardware reciprocal by batch inversion, with wdiffr clamped to
-// >= 1/4 (exact for every branch-A term) so the product is safe, and
-// masked terms select r = 0.  Occupied bands (n < nvband) also evaluate the
+// single hardware reciprocal by batch inversion (gpp_device.h: unclamped
+// denominators, a lane test on (Im om)^2 for the product's range), and
+// masked terms clear the reciprocal's high word.  Occupied bands (n < nvband) also evaluate the
 // screened-exchange term with full complex arithmetic.
 //
 // Each workgroup (4 waves) writes one partial per output into the
@@ -34,11 +35,16 @@ namespace gpp {
 
 constexpr int kFwdWaves = 4;
 constexpr int kFwdThreads = kFwdWaves * kWave;
-// Bands per batch-inverted group (K = bands * nfreq reciprocals from one
-// hardware reciprocal) and an optional cap on VGPRs through a minimum
-// number of waves per SIMD; chosen by measurement on MI355X.
+// G' columns per wave tile and bands per batch-inverted group (K = bands *
+// nfreq reciprocals from one hardware reciprocal) for nfreq <= 3, and an
+// optional cap on VGPRs through a minimum number of waves per SIMD; chosen
+// by measurement on MI355X.  Two columns per wave let each aqsntemp load
+// serve both: 148 VGPRs (3 waves per SIMD) at nfreq 3 with 2-band groups,
+// 2.8-3.1 % faster than one column with 3-band groups (105 VGPRs, 4 waves).
+// With 4 or more frequencies a second column would leave 2 waves or fewer,
+// so those keep one column.
 #ifndef GPP_FWD_BANDS
-#define GPP_FWD_BANDS 3
+#define GPP_FWD_BANDS 2
 #endif
 #ifndef GPP_FWD_MIN_WAVES
 #define GPP_FWD_MIN_WAVES 1
@@ -67,11 +73,21 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
 
     if (tile < ntiles) {
         // consecutive tiles share a g-tile (and so the same aqsntemp rows)
-        const int gt = (int)(tile / np);
-        const int p = (int)(tile - (long)gt * np);
-        fwd_tile_body<NW, BU>(nb, nv, ng, p, gt, lane, as_global(aqsm), as_global(aqsn),
-                              as_global(ieps), as_global(wt), as_global(vcoul), as_global(wx),
-                              ach, asx);
+        constexpr int C = fwd_cols(NW);
+        const int npt = (np + C - 1) / C;  // column tiles per g-tile
+        const int gt = (int)(tile / npt);
+        const int pt = (int)(tile - (long)gt * npt);
+        if (C == 1) {
+            fwd_tile_body<NW, BU>(nb, nv, ng, pt, gt, lane, as_global(aqsm), as_global(aqsn),
+                                  as_global(ieps), as_global(wt), as_global(vcoul),
+                                  as_global(wx), ach, asx);
+        } else {
+            const int p0 = 2 * pt;
+            const bool has1 = p0 + 1 < np;
+            fwd_tile_body_c2<NW, BU>(nb, nv, ng, p0, has1 ? p0 + 1 : p0, has1, gt, lane,
+                                     as_global(aqsm), as_global(aqsn), as_global(ieps),
+                                     as_global(wt), as_global(vcoul), as_global(wx), ach, asx);
+        }
     }
 
     // wave then workgroup reduction in a fixed order; partial row layout
@@ -153,7 +169,8 @@ FwdGeometry fwd_geometry(const Dims32 &d)
     FwdGeometry geo{};
     if (d.nb == 0 || d.ng == 0 || d.np == 0) return geo;
     const long gtiles = (d.ng + kWave - 1) / kWave;
-    geo.ntiles = gtiles * d.np;
+    const int cols = fwd_cols(d.nw);
+    geo.ntiles = gtiles * ((d.np + cols - 1) / cols);
     geo.nblocks = (geo.ntiles + kFwdWaves - 1) / kFwdWaves;
     geo.red_blocks = geo.nblocks < kRedBlocks ? geo.nblocks : kRedBlocks;
     geo.red_chunk = (geo.nblocks + geo.red_blocks - 1) / geo.red_blocks;

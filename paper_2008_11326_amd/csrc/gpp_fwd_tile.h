@@ -79,6 +79,46 @@ __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aq
     ch_group_an<NW, BU>(n, nb, ng, an, am_col, wx, a, wi2, thr, wide, P1, P2);
 }
 
+// Occupied bands n < nv of one lane and one column: Coulomb-hole terms into
+// P1/P2 and screened-exchange terms (ssx / e) into SX, with full complex
+// arithmetic and one reciprocal per term.
+template <int NW>
+__device__ __forceinline__ void occupied_bands(int nv, int nb, int ng, gptr<double2> an_col,
+                                               gptr<double2> am_col, gptr<double> wx, cplx om,
+                                               double wi2, double wtr, double thr,
+                                               cplx (&P1)[NW], cplx (&P2)[NW], cplx (&SX)[NW])
+{
+    const double a = om.re, b = om.im;
+    for (int n = 0; n < nv; ++n) {
+        const cplx an = cload(an_col + (size_t)n * ng);
+        const cplx am = cload(am_col + (size_t)n * ng);
+        const cplx qm = cmul_conj(an, am);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const double x = wx[(size_t)w * nb + n];
+            const double dr = x - a;
+            const double wd = fma(dr, dr, wi2);
+            const bool isA = wd > thr;
+            const double r = isA ? rcp_nr2(wd) : 0.0;
+            const double rx = r * x;
+            P1[w].re = fma(rx, qm.re, P1[w].re);
+            P1[w].im = fma(rx, qm.im, P1[w].im);
+            P2[w].re = fma(r, qm.re, P2[w].re);
+            P2[w].im = fma(r, qm.im, P2[w].im);
+            // ssx / e
+            const cplx d = cmake(dr, -b);    // x - om
+            const cplx s = cmake(x + a, b);  // x + om
+            cplx t = cmake(0.0, 0.0);
+            if (isA) {
+                t = cdiv(cmul(om, om), cmul(d, s));
+            } else if (branch_b_holds(wtr, wd)) {
+                t = cdiv(om, cmake(-2.0 * s.re, -2.0 * s.im));
+            }
+            cmac(SX[w], qm, t);
+        }
+    }
+}
+
 // One tile: lane g = gt*64 + lane of column p.  On return ach[w] holds this
 // lane's Coulomb-hole contribution (still to be summed over the wave) and
 // asx[w] the wave's screened-exchange total (wave-uniform).  Must be called
@@ -112,34 +152,7 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
     const cplx ev = cscale(v, e);
 
     // occupied bands: screened exchange (SX) and Coulomb hole (CH)
-    for (int n = 0; n < nv; ++n) {
-        const cplx an = cload(an_col + (size_t)n * ng);
-        const cplx am = cload(am_col + (size_t)n * ng);
-        const cplx qm = cmul_conj(an, am);
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const double x = wx[(size_t)w * nb + n];
-            const double dr = x - a;
-            const double wd = fma(dr, dr, wi2);
-            const bool isA = wd > thr;
-            const double r = isA ? rcp_nr2(wd) : 0.0;
-            const double rx = r * x;
-            P1[w].re = fma(rx, qm.re, P1[w].re);
-            P1[w].im = fma(rx, qm.im, P1[w].im);
-            P2[w].re = fma(r, qm.re, P2[w].re);
-            P2[w].im = fma(r, qm.im, P2[w].im);
-            // ssx / e
-            const cplx d = cmake(dr, -b);    // x - om
-            const cplx s = cmake(x + a, b);  // x + om
-            cplx t = cmake(0.0, 0.0);
-            if (isA) {
-                t = cdiv(cmul(om, om), cmul(d, s));
-            } else if (branch_b_holds(wtr, wd)) {
-                t = cdiv(om, cmake(-2.0 * s.re, -2.0 * s.im));
-            }
-            cmac(SX[w], qm, t);
-        }
-    }
+    occupied_bands<NW>(nv, nb, ng, an_col, am_col, wx, om, wi2, wtr, thr, P1, P2, SX);
     // The exchange sums are finished here and reduced over the wave into
     // scalar registers, so they hold no vector registers in the hot loop.
     if (nv > 0) {
@@ -184,6 +197,109 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
         S.re = fma(-wtr, P2[w].re, S.re);
         S.im = fma(-wtr, P2[w].im, S.im);
         ach[w] = cscale(0.5, cmul(ev, S));
+    }
+}
+
+// Two G' columns p0 and p1 of one 64-row tile per wave: each aqsntemp
+// element a lane loads serves both columns, which halves the vector-memory
+// traffic of the hot loop.  With has1 false (p0 is the last column) p1 must
+// equal p0 and its contribution is dropped.  Outputs as fwd_tile_body, for
+// both columns together.
+template <int NW, int BU>
+__device__ __forceinline__ void fwd_tile_body_c2(int nb, int nv, int ng, int p0, int p1,
+                                                 bool has1, int gt, int lane,
+                                                 gptr<double2> aqsm, gptr<double2> aqsn,
+                                                 gptr<double2> ieps, gptr<double2> wt,
+                                                 gptr<double> vcoul, gptr<double> wx,
+                                                 cplx (&ach)[NW], cplx (&asx)[NW])
+{
+    const int g = gt * kWave + lane;
+    const bool valid = g < ng;
+    const int gc = valid ? g : ng - 1;  // clamped, contribution zeroed
+    const int pc[2] = {p0, p1};
+
+    cplx om[2];
+    double a[2], wi2[2], thr[2];
+    bool wide[2];
+    cplx P1[2][NW], P2[2][NW];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        om[c] = cload(wt + (size_t)pc[c] * ng + gc);
+        a[c] = om[c].re;
+        wi2[c] = om[c].im * om[c].im;
+        thr[c] = branch_a_threshold(fma(a[c], a[c], wi2[c]));
+        wide[c] = wi2[c] >= kMinUnclampedWi2;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) P1[c][w] = P2[c][w] = cmake(0.0, 0.0);
+    }
+    const gptr<double2> an_col = aqsn + gc;
+    const uint32_t goff = (uint32_t)gc * (uint32_t)sizeof(double2);
+    const double v = valid ? vcoul[gc] : 0.0;
+
+    // occupied bands, column by column; the exchange sums of both columns
+    // are reduced over the wave into scalar registers before the hot loop
+    if (nv > 0) {
+        cplx sx[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sx[w] = cmake(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            cplx SX[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) SX[w] = cmake(0.0, 0.0);
+            occupied_bands<NW>(nv, nb, ng, an_col, aqsm + pc[c], wx, om[c], wi2[c],
+                               fma(a[c], a[c], wi2[c]), thr[c], P1[c], P2[c], SX);
+            const double vc = (c == 0 || has1) ? v : 0.0;
+            const cplx ev = cscale(vc, cload(ieps + (size_t)pc[c] * ng + gc));
+#pragma unroll
+            for (int w = 0; w < NW; ++w) cmac(sx[w], ev, SX[w]);
+        }
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            asx[w] = cmake(wave_sum_uniform(sx[w].re), wave_sum_uniform(sx[w].im));
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) asx[w] = cmake(0.0, 0.0);
+    }
+
+    // unoccupied bands: CH only
+    int n = nv;
+    for (; n + BU <= nb; n += BU) {
+        cplx an[BU];
+        load_an<BU>(n, ng, aqsn, goff, an);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            ch_group_an<NW, BU>(n, nb, ng, an, aqsm + pc[c], wx, a[c], wi2[c], thr[c], wide[c],
+                                P1[c], P2[c]);
+            // one column's reciprocal chain at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    for (; n < nb; ++n) {
+        cplx an[1];
+        load_an<1>(n, ng, aqsn, goff, an);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            ch_group_an<NW, 1>(n, nb, ng, an, aqsm + pc[c], wx, a[c], wi2[c], thr[c], wide[c],
+                               P1[c], P2[c]);
+    }
+
+#pragma unroll
+    for (int w = 0; w < NW; ++w) ach[w] = cmake(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double vc = (c == 0 || has1) ? v : 0.0;
+        const cplx ev = cscale(vc, cload(ieps + (size_t)pc[c] * ng + gc));
+        const double wtr = fma(a[c], a[c], wi2[c]);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            // S = om P1 - wtr P2
+            cplx S = cmul(om[c], P1[c][w]);
+            S.re = fma(-wtr, P2[c][w].re, S.re);
+            S.im = fma(-wtr, P2[c][w].im, S.im);
+            const cplx t = cscale(0.5, cmul(ev, S));
+            ach[w] = cadd(ach[w], t);
+        }
     }
 }
 

@@ -81,6 +81,27 @@ const void *batched_kernel(int nw, int bu, int sched);
 hipError_t launch_batched(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st);
 constexpr int kXcdCount = 8;
 
+// G' columns per forward wave tile for nfreq frequencies, shared by the
+// plain and batched forwards and the plan's tile counts.  Two columns let
+// each aqsntemp load serve both; with more than three frequencies a second
+// column's accumulators would leave two waves per SIMD or fewer.
+#ifndef GPP_FWD_COLS
+#define GPP_FWD_COLS 2
+#endif
+constexpr int fwd_cols(int nw) { return nw <= 3 ? GPP_FWD_COLS : 1; }
+// The same for the batched persistent forward's tiles, and the register cap
+// (minimum waves per SIMD) of its two-column form.  The batched kernel keeps
+// one column: with two, its persistent loop runs out of scalar registers,
+// the per-band aqsmtemp and aqsntemp loads become per-lane vector loads, and
+// it measured 30 % slower (640-690 ms against 494 ms on 64 states).
+#ifndef GPP_BAT_COLS
+#define GPP_BAT_COLS 1
+#endif
+#ifndef GPP_BAT_WAVES2
+#define GPP_BAT_WAVES2 3
+#endif
+constexpr int bat_cols(int nw) { return nw <= 3 ? GPP_BAT_COLS : 1; }
+
 // host-side validation and error reporting shared by the entry points
 extern thread_local char g_last_error[512];
 gpp_status fail(gpp_status s, const char *fmt, ...);

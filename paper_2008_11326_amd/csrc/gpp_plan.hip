@@ -516,7 +516,8 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
             delete pl;
             return fail(GPP_ERR_INVALID, "state %d: nfreq differs from state 0", s);
         }
-        pl->tiles[s] = (d.nb && d.ng && d.np) ? (long)((d.ng + 63) / 64) * d.np : 0;
+        const int cols = gpp::bat_cols(d.nw);
+        pl->tiles[s] = (d.nb && d.ng && d.np) ? (long)((d.ng + 63) / 64) * ((d.np + cols - 1) / cols) : 0;
         pl->total_tiles += pl->tiles[s];
     }
     pl->nw = pl->dims[0].nw;
@@ -535,7 +536,8 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
     // candidates: bands per group (register budget allows fewer for many
     // frequencies) x schedule order; the first is the untuned default
     std::vector<int> bus;
-    if (pl->nw <= 3) bus = {3, 2};
+    if (pl->nw <= 3 && gpp::bat_cols(pl->nw) == 2) bus = {2, 1};  // 3-band groups spill
+    else if (pl->nw <= 3) bus = {3, 2};
     else if (pl->nw == 4) bus = {2, 1};
     else bus = {1};
     long nchunks = 0;
@@ -564,8 +566,8 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
     uint64_t h = fnv1a(&pl->nw, sizeof pl->nw);
     for (const auto &d : pl->dims) h = fnv1a(&d, sizeof d, h);
     char key[160];
-    snprintf(key, sizeof key, "gfx950:batched:nw=%d:n=%d:cus=%d:h=%016llx", pl->nw, nstates,
-             prop.multiProcessorCount, (unsigned long long)h);
+    snprintf(key, sizeof key, "gfx950:batched:nw=%d:cols=%d:n=%d:cus=%d:h=%016llx", pl->nw,
+             gpp::bat_cols(pl->nw), nstates, prop.multiProcessorCount, (unsigned long long)h);
     pl->key = key;
 
     const size_t sbytes = sizeof(gpp::StateDesc) * (nstates + 1);

@@ -160,6 +160,26 @@ def test_bwd_workspace_grows_with_rows_bands_columns(lib):
     assert lib.gpp_sigma_bwd_workspace(None) == 0
 
 
+def _bwd_segments(lib, nb, nv, ng, npw, nw):
+    """Segments of the aqsntemp-gradient pass's G' range, read back from the
+    workspace size: the unsplit layout plus S * nb * ng complex partials."""
+    up = lambda e: (e * 16 + 255) // 256 * 256
+    unsplit = up(nw) + up(nw * nb) + up(((ng + 255) // 256) * nb * npw)
+    extra = lib.gpp_sigma_bwd_workspace(C.byref(_dims(nb, nv, ng, npw, nw))) - unsplit
+    return 1 if extra == 0 else extra // (16 * nb * ng)
+
+
+def test_bwd_bands_pass_segments(lib):
+    # ~16 rounds of 5120 resident waves, segments of >= 64 G' columns
+    assert _bwd_segments(lib, 256, 2, 16384, 819, 3) == 4      # adjoint workload
+    assert _bwd_segments(lib, 512, 2, 32768, 1638, 3) == 1     # Si-shaped: grid already long
+    assert _bwd_segments(lib, 1024, 4, 65536, 3276, 3) == 1
+    assert _bwd_segments(lib, 9, 2, 200, 130, 3) == 2          # capped by 130 // 64
+    assert _bwd_segments(lib, 13, 2, 300, 200, 3) == 3
+    assert _bwd_segments(lib, 32, 2, 512, 63, 3) == 1          # fewer than 2 x 64 columns
+    assert lib.gpp_sigma_bwd_workspace(C.byref(_dims(256, 2, 16384, 819, 3))) == 483143936
+
+
 def test_plan_validation_before_any_device_call(lib):
     handle = C.c_void_p(123)
     bad = (_lib.GppDims * 2)(_lib.GppDims(8, 2, 100, 10, 3), _lib.GppDims(8, 9, 100, 10, 3))

@@ -71,6 +71,29 @@ def test_every_entry_small(gpp, shape, poles):
     assert np.all(g["aqsmtemp"][:, npw:] == 0)
 
 
+@pytest.mark.parametrize("shape,poles", [
+    ((9, 2, 200, 130, 3), 0.0),    # 2 segments of the G' range, whole band tiles
+    ((13, 2, 300, 200, 3), 0.1),   # 3 segments (66/67/67 columns), ragged last band tile
+])
+def test_every_entry_segmented_bands_pass(gpp, shape, poles):
+    """Shapes small enough that the aqsntemp-gradient pass splits its G'
+    range into segments (partial sums added in segment order)."""
+    nb, nv, ng, npw, nw = shape
+    up = lambda e: (e * 16 + 255) // 256 * 256
+    unsplit = up(nw) + up(nw * nb) + up(((ng + 255) // 256) * nb * npw)
+    assert gpp.bwd_workspace_bytes(*shape) - unsplit >= 2 * nb * ng * 16, "expected a segmented pass"
+    prob = I.make_problem(I.Dims(*shape), sum(shape) + 11, poles)
+    rng = np.random.default_rng(11)
+    ga, gs = I.make_upstream_grad(prob.dims.nfreq, rng)
+    say(f"[bwd] segmented {shape} poles={poles}")
+    g = gpu_grads(gpp, prob, ga, gs)
+    check_entries("aqsntemp", g["aqsntemp"], prob, ga, gs, all_entries(nb, ng))
+    check_entries("aqsmtemp", g["aqsmtemp"], prob, ga, gs, all_entries(nb, npw))
+    idx = np.random.default_rng(5).integers(0, [npw, ng], size=(400, 2))
+    check_entries("I_eps_array", g["I_eps_array"], prob, ga, gs, idx)
+    check_entries("wtilde_array", g["wtilde_array"], prob, ga, gs, idx)
+
+
 @pytest.mark.parametrize("frac", [0.05, 0.5, 1.0])
 def test_every_entry_tiny_imaginary_lanes(gpp, frac):
     """Lanes whose (Im om)^2 is below 2^-60 (real om, exact poles, |Im om|

@@ -63,11 +63,10 @@ __device__ __forceinline__ void state_tile(const StateDesc &d, long local, int l
                               as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
                               as_global(d.vcoul), as_global(d.wx), a, x);
     } else {
-        const int p0 = 2 * pt;
-        const bool has1 = p0 + 1 < d.np;
-        fwd_tile_body_c2<NW, BU>(d.nb, d.nv, d.ng, p0, has1 ? p0 + 1 : p0, has1, gt, lane,
-                                 as_global(d.aqsm), as_global(d.aqsn), as_global(d.ieps),
-                                 as_global(d.wt), as_global(d.vcoul), as_global(d.wx), a, x);
+        fwd_tile_body_cols<NW, BU, C>(d.nb, d.nv, d.ng, d.np, C * pt, gt, lane,
+                                      as_global(d.aqsm), as_global(d.aqsn), as_global(d.ieps),
+                                      as_global(d.wt), as_global(d.vcoul), as_global(d.wx), a,
+                                      x);
     }
 }
 

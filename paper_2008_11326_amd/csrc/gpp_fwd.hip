@@ -41,6 +41,7 @@ constexpr int kFwdThreads = kFwdWaves * kWave;
 // by measurement on MI355X.  Two columns per wave let each aqsntemp load
 // serve both: 148 VGPRs (3 waves per SIMD) at nfreq 3 with 2-band groups,
 // 2.8-3.1 % faster than one column with 3-band groups (105 VGPRs, 4 waves).
+// Three columns need about 200 VGPRs (2 waves) and measured 3-30 % slower.
 // With 4 or more frequencies a second column would leave 2 waves or fewer,
 // so those keep one column.
 #ifndef GPP_FWD_BANDS
@@ -82,11 +83,9 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
                                   as_global(ieps), as_global(wt), as_global(vcoul),
                                   as_global(wx), ach, asx);
         } else {
-            const int p0 = 2 * pt;
-            const bool has1 = p0 + 1 < np;
-            fwd_tile_body_c2<NW, BU>(nb, nv, ng, p0, has1 ? p0 + 1 : p0, has1, gt, lane,
-                                     as_global(aqsm), as_global(aqsn), as_global(ieps),
-                                     as_global(wt), as_global(vcoul), as_global(wx), ach, asx);
+            fwd_tile_body_cols<NW, BU, C>(nb, nv, ng, np, C * pt, gt, lane, as_global(aqsm),
+                                          as_global(aqsn), as_global(ieps), as_global(wt),
+                                          as_global(vcoul), as_global(wx), ach, asx);
         }
     }
 

@@ -200,30 +200,33 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
     }
 }
 
-// Two G' columns p0 and p1 of one 64-row tile per wave: each aqsntemp
-// element a lane loads serves both columns, which halves the vector-memory
-// traffic of the hot loop.  With has1 false (p0 is the last column) p1 must
-// equal p0 and its contribution is dropped.  Outputs as fwd_tile_body, for
-// both columns together.
-template <int NW, int BU>
-__device__ __forceinline__ void fwd_tile_body_c2(int nb, int nv, int ng, int p0, int p1,
-                                                 bool has1, int gt, int lane,
-                                                 gptr<double2> aqsm, gptr<double2> aqsn,
-                                                 gptr<double2> ieps, gptr<double2> wt,
-                                                 gptr<double> vcoul, gptr<double> wx,
-                                                 cplx (&ach)[NW], cplx (&asx)[NW])
+// NC consecutive G' columns p0 .. p0+NC-1 of one 64-row tile per wave:
+// each aqsntemp element a lane loads serves all of them, which divides the
+// vector-memory traffic of the hot loop by NC.  Columns at or beyond np
+// repeat p0 and their contribution is dropped.  Outputs as fwd_tile_body,
+// for the NC columns together.
+template <int NW, int BU, int NC>
+__device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int np, int p0,
+                                                   int gt, int lane, gptr<double2> aqsm,
+                                                   gptr<double2> aqsn, gptr<double2> ieps,
+                                                   gptr<double2> wt, gptr<double> vcoul,
+                                                   gptr<double> wx, cplx (&ach)[NW],
+                                                   cplx (&asx)[NW])
 {
     const int g = gt * kWave + lane;
     const bool valid = g < ng;
     const int gc = valid ? g : ng - 1;  // clamped, contribution zeroed
-    const int pc[2] = {p0, p1};
 
-    cplx om[2];
-    double a[2], wi2[2], thr[2];
-    bool wide[2];
-    cplx P1[2][NW], P2[2][NW];
+    int pc[NC];
+    bool has[NC];
+    cplx om[NC];
+    double a[NC], wi2[NC], thr[NC];
+    bool wide[NC];
+    cplx P1[NC][NW], P2[NC][NW];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < NC; ++c) {
+        has[c] = p0 + c < np;
+        pc[c] = has[c] ? p0 + c : p0;
         om[c] = cload(wt + (size_t)pc[c] * ng + gc);
         a[c] = om[c].re;
         wi2[c] = om[c].im * om[c].im;
@@ -236,20 +239,20 @@ __device__ __forceinline__ void fwd_tile_body_c2(int nb, int nv, int ng, int p0,
     const uint32_t goff = (uint32_t)gc * (uint32_t)sizeof(double2);
     const double v = valid ? vcoul[gc] : 0.0;
 
-    // occupied bands, column by column; the exchange sums of both columns
+    // occupied bands, column by column; the exchange sums of all columns
     // are reduced over the wave into scalar registers before the hot loop
     if (nv > 0) {
         cplx sx[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) sx[w] = cmake(0.0, 0.0);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
             cplx SX[NW];
 #pragma unroll
             for (int w = 0; w < NW; ++w) SX[w] = cmake(0.0, 0.0);
             occupied_bands<NW>(nv, nb, ng, an_col, aqsm + pc[c], wx, om[c], wi2[c],
                                fma(a[c], a[c], wi2[c]), thr[c], P1[c], P2[c], SX);
-            const double vc = (c == 0 || has1) ? v : 0.0;
+            const double vc = has[c] ? v : 0.0;
             const cplx ev = cscale(vc, cload(ieps + (size_t)pc[c] * ng + gc));
 #pragma unroll
             for (int w = 0; w < NW; ++w) cmac(sx[w], ev, SX[w]);
@@ -268,7 +271,7 @@ __device__ __forceinline__ void fwd_tile_body_c2(int nb, int nv, int ng, int p0,
         cplx an[BU];
         load_an<BU>(n, ng, aqsn, goff, an);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NC; ++c) {
             ch_group_an<NW, BU>(n, nb, ng, an, aqsm + pc[c], wx, a[c], wi2[c], thr[c], wide[c],
                                 P1[c], P2[c]);
             // one column's reciprocal chain at a time (register pressure)
@@ -279,7 +282,7 @@ __device__ __forceinline__ void fwd_tile_body_c2(int nb, int nv, int ng, int p0,
         cplx an[1];
         load_an<1>(n, ng, aqsn, goff, an);
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < NC; ++c)
             ch_group_an<NW, 1>(n, nb, ng, an, aqsm + pc[c], wx, a[c], wi2[c], thr[c], wide[c],
                                P1[c], P2[c]);
     }
@@ -287,8 +290,8 @@ __device__ __forceinline__ void fwd_tile_body_c2(int nb, int nv, int ng, int p0,
 #pragma unroll
     for (int w = 0; w < NW; ++w) ach[w] = cmake(0.0, 0.0);
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const double vc = (c == 0 || has1) ? v : 0.0;
+    for (int c = 0; c < NC; ++c) {
+        const double vc = has[c] ? v : 0.0;
         const cplx ev = cscale(vc, cload(ieps + (size_t)pc[c] * ng + gc));
         const double wtr = fma(a[c], a[c], wi2[c]);
 #pragma unroll

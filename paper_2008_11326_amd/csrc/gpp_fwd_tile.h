@@ -1,7 +1,7 @@
-// gpp_fwd_tile.h -- the forward work of one wave tile (one G' column p x
-// 64 consecutive G rows), shared by the plain forward and the persistent
-// batched kernel so both run the same arithmetic.  See gpp_fwd.hip for
-// the derivation.
+// gpp_fwd_tile.h -- the forward work of one wave tile (one or several G'
+// columns x 64 consecutive G rows), shared by the plain forward and the
+// persistent batched kernel so both run the same arithmetic.  See
+// gpp_fwd.hip for the derivation.
 #pragma once
 
 #include "gpp_device.h"

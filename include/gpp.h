@@ -152,10 +152,13 @@ typedef struct gpp_plan gpp_plan;
  * gpp_plan_create -- plan a batched forward for `nstates` states whose
  * sizes are dims_host[0..nstates-1] (host array; every state must share
  * nfreq).  Queries the current device (must be gfx950), sizes the
- * persistent grid to the kernel's resident capacity, and allocates the
+ * persistent grids to the kernels' resident capacity, and allocates the
  * plan's device descriptor table, pinned staging buffer and capture
  * stream.  The schedule is tuned on the first gpp_sigma_batched call (or
- * taken from the tuning cache, see below).  *out is NULL on failure.
+ * taken from the tuning cache, see below).  Candidates: the flat grid (the
+ * untuned default) and the persistent schedules 0-3 of gpp_plan_info, each
+ * with its tile variants; the environment variable GPP_BATCHED_SCHEDULE=<n>
+ * keeps only schedule n (and bypasses the cache).  *out is NULL on failure.
  */
 gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan **out);
 
@@ -167,13 +170,17 @@ typedef struct {
     int32_t from_cache;       /* 1 if the choice came from the tuning cache  */
     int32_t bands_per_group;  /* tile variant of the chosen candidate        */
     int32_t schedule_order;   /* 0 = caller order, 1 = longest tiles first   */
-    int32_t workgroups;       /* persistent workgroups (4 waves each)        */
+    int32_t workgroups;       /* persistent workgroups (4 waves each); for
+                                 the flat schedule, all of its workgroups     */
     int32_t waves;
     int32_t candidates;       /* size of the search space                    */
     int32_t schedule;         /* 0 = global round-robin, 1 = one contiguous
                                  chunk of the tile list per XCD, 2 = work
                                  queue of 2-tile chunks, 3 = one such queue
-                                 per XCD (own region first, then stealing)   */
+                                 per XCD (own region first, then stealing),
+                                 4 = flat grid (not persistent: one
+                                 workgroup per four tiles of the plain
+                                 forward's shape)                            */
     int64_t total_tiles;      /* 64-row wave tiles over all states           */
     double tuned_ms;          /* measured time of the chosen candidate       */
 } gpp_plan_info;

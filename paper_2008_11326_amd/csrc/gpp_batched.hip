@@ -24,7 +24,11 @@
 
 namespace gpp {
 
+#ifndef GPP_BAT_FLAT_RUN
+#define GPP_BAT_FLAT_RUN 16
+#endif
 constexpr int kBatWaves = 4;
+constexpr long kFlatRun = GPP_BAT_FLAT_RUN;  // flat form: consecutive workgroups per XCD
 constexpr int kBatThreads = kBatWaves * kWave;
 
 // Write the wave's running sums for state s (wave-uniform values) and
@@ -195,6 +199,86 @@ batched_queue(const StateDesc *__restrict__ st, long nchunks, int chunk_tiles,
     }
 }
 
+// Flat form (not persistent): one wave per tile of the plain forward's own
+// shape (fwd_cols(NW) G' columns x 64 rows, fwd_tile_body_cols), four
+// consecutive tiles of one state per workgroup, each state's tiles padded to
+// whole workgroups.  Here chunk_begin is a state's first workgroup:
+// workgroup wg finds its state by binary search, and writes one partial row
+// (zeros past the state's last tile), which batched_reduce_chunks adds per
+// state in a fixed order.  With no loop state to carry it keeps the plain
+// forward's registers and two-column tiles.
+template <int NW, int BU>
+__global__ void __launch_bounds__(kBatThreads)
+batched_flat(const StateDesc *__restrict__ st, int nstates, double *__restrict__ partials)
+{
+    __shared__ double red[kBatWaves][4 * NW];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // Workgroups reach the XCDs round-robin.  Within each span of
+    // 8 * kFlatRun workgroups, XCD x takes the kFlatRun consecutive ones
+    // starting at x * kFlatRun (neighbouring tiles share rows in its L2),
+    // while across spans every XCD keeps meeting every state of the
+    // cost-ordered list (contiguous per-XCD ranges of the whole grid would
+    // give the first XCD all the most expensive states).  The last, partial
+    // span keeps the identity.
+    const long b = blockIdx.x, span = (long)kXcdCount * kFlatRun;
+    const long sb = b / span;
+    long wg = b;
+    if ((sb + 1) * span <= (long)gridDim.x) {
+        const long r = b - sb * span;
+        wg = sb * span + (r % kXcdCount) * kFlatRun + r / kXcdCount;
+    }
+    // st[lo].chunk_begin <= wg < st[hi].chunk_begin; st[nstates] is the
+    // sentinel holding the total, so the state found owns wg
+    int lo = 0, hi = nstates;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (st[mid].chunk_begin <= wg) lo = mid;
+        else hi = mid;
+    }
+    const StateDesc d = st[lo];
+    constexpr int C = fwd_cols(NW);
+    const int npt = (d.np + C - 1) / C;
+    const long ntile = (long)((d.ng + kWave - 1) / kWave) * npt;
+    const long local = (wg - d.chunk_begin) * kBatWaves + wid;
+
+    cplx ach[NW], asx[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
+    if (local < ntile) {
+        const int gt = (int)(local / npt);
+        const int pt = (int)(local - (long)gt * npt);
+        if (C == 1) {
+            fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, pt, gt, lane, as_global(d.aqsm),
+                                  as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
+                                  as_global(d.vcoul), as_global(d.wx), ach, asx);
+        } else {
+            fwd_tile_body_cols<NW, BU, C>(d.nb, d.nv, d.ng, d.np, C * pt, gt, lane,
+                                          as_global(d.aqsm), as_global(d.aqsn),
+                                          as_global(d.ieps), as_global(d.wt),
+                                          as_global(d.vcoul), as_global(d.wx), ach, asx);
+        }
+    }
+    // wave then workgroup sums in a fixed order (row layout as the other forms)
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const double v0 = wave_sum(ach[w].re), v1 = wave_sum(ach[w].im);
+        if (lane == 0) {
+            red[wid][4 * w + 0] = v0;
+            red[wid][4 * w + 1] = v1;
+            red[wid][4 * w + 2] = asx[w].re;  // already wave totals
+            red[wid][4 * w + 3] = asx[w].im;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 * NW) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBatWaves; ++k) s += red[k][threadIdx.x];
+        partials[(size_t)wg * 4 * NW + threadIdx.x] = s;
+    }
+}
+
 __global__ void zero_counters(unsigned long long *counter, int n)
 {
     if ((int)threadIdx.x < n) counter[threadIdx.x] = 0ull;
@@ -274,6 +358,7 @@ batched_reduce(const double *__restrict__ partials, int nwaves, double2 *__restr
 template <int NW, int BU>
 static const void *persistent_ptr(int sched)
 {
+    if (sched == kSchedFlat) return reinterpret_cast<const void *>(&batched_flat<NW, BU>);
     return (sched == kSchedQueue || sched == kSchedXcdQueues)
                ? reinterpret_cast<const void *>(&batched_queue<NW, BU>)
                : reinterpret_cast<const void *>(&batched_persistent<NW, BU>);
@@ -297,7 +382,7 @@ const void *batched_kernel(int nw, int bu, int sched)
 template <int NW>
 static void launch_reduce(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st)
 {
-    if (L.sched == kSchedQueue || L.sched == kSchedXcdQueues)
+    if (L.sched == kSchedQueue || L.sched == kSchedXcdQueues || L.sched == kSchedFlat)
         hipLaunchKernelGGL(batched_reduce_chunks<NW>, dim3(L.nstates), dim3(256), 0, st, L.desc,
                            L.partials, ach, asx);
     else
@@ -310,7 +395,16 @@ hipError_t launch_batched(const BatchedLaunch &L, double2 *ach, double2 *asx, hi
     const void *k = batched_kernel(L.nw, L.bu, L.sched);
     if (!k) return hipErrorInvalidValue;
     hipError_t e;
-    if (L.sched == kSchedQueue || L.sched == kSchedXcdQueues) {
+    if (L.sched == kSchedFlat) {
+        // L.nchunks workgroups; none for an all-empty plan (the reduction
+        // then writes zeros)
+        if (L.nchunks > 0) {
+            void *args[] = {(void *)&L.desc, (void *)&L.nstates, (void *)&L.partials};
+            e = hipLaunchKernel(k, dim3((unsigned)L.nchunks), dim3(kBatThreads), args, 0, st);
+        } else {
+            e = hipSuccess;
+        }
+    } else if (L.sched == kSchedQueue || L.sched == kSchedXcdQueues) {
         hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, st, L.counter, kXcdCount);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const long *qb = L.sched == kSchedXcdQueues ? L.queue_begin : nullptr;

@@ -36,21 +36,18 @@ namespace gpp {
 constexpr int kFwdWaves = 4;
 constexpr int kFwdThreads = kFwdWaves * kWave;
 // G' columns per wave tile and bands per batch-inverted group (K = bands *
-// nfreq reciprocals from one hardware reciprocal) for nfreq <= 3, and an
-// optional cap on VGPRs through a minimum number of waves per SIMD; chosen
-// by measurement on MI355X.  Two columns per wave let each aqsntemp load
+// nfreq reciprocals from one hardware reciprocal) for nfreq <= 3 come from
+// fwd_cols and fwd_bands (gpp_internal.h), and an optional cap on VGPRs
+// through a minimum number of waves per SIMD; chosen by measurement on
+// MI355X.  Two columns per wave let each aqsntemp load
 // serve both: 148 VGPRs (3 waves per SIMD) at nfreq 3 with 2-band groups,
 // 2.8-3.1 % faster than one column with 3-band groups (105 VGPRs, 4 waves).
 // Three columns need about 200 VGPRs (2 waves) and measured 3-30 % slower.
 // With 4 or more frequencies a second column would leave 2 waves or fewer,
 // so those keep one column.
-#ifndef GPP_FWD_BANDS
-#define GPP_FWD_BANDS 2
-#endif
 #ifndef GPP_FWD_MIN_WAVES
 #define GPP_FWD_MIN_WAVES 1
 #endif
-constexpr int kFwdBands = GPP_FWD_BANDS;
 constexpr int kRedThreads = 256;
 constexpr long kRedBlocks = 512;  // first reduction stage
 
@@ -186,7 +183,7 @@ static hipError_t launch_fwd_nw(const Dims32 &d, const FwdGeometry &geo, const D
 {
     double *partials = ws;
     double *stage = ws + (size_t)geo.nblocks * 4 * NW;
-    constexpr int BU = NW <= 3 ? kFwdBands : (NW <= 4 ? 2 : 1);
+    constexpr int BU = fwd_bands(NW);
     hipLaunchKernelGGL((fwd_tiles<NW, BU>), dim3((unsigned)geo.nblocks),
                        dim3(kFwdThreads), 0, st, d.nb, d.nv, d.ng, d.np, geo.ntiles, in.aqsm,
                        in.aqsn, in.ieps, in.wt, in.vcoul, in.wx, partials);

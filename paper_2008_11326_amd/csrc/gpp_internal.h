@@ -62,7 +62,9 @@ enum BatchedSchedule {
     kSchedXcdChunks = 1,   // one equal-cost contiguous chunk per XCD
     kSchedQueue = 2,       // waves take chunk_tiles-tile chunks from a counter
     kSchedXcdQueues = 3,   // one such queue per XCD over its own region, with stealing
+    kSchedFlat = 4,        // not persistent: one workgroup per four tiles of one state
 };
+constexpr int kSchedCount = 5;
 
 struct BatchedLaunch {
     int nw, bu, blocks, sched;
@@ -89,6 +91,12 @@ constexpr int kXcdCount = 8;
 #define GPP_FWD_COLS 2
 #endif
 constexpr int fwd_cols(int nw) { return nw <= 3 ? GPP_FWD_COLS : 1; }
+// Bands per batch-inverted group of the plain forward (and of the batched
+// flat form, which runs the same tiles).
+#ifndef GPP_FWD_BANDS
+#define GPP_FWD_BANDS 2
+#endif
+constexpr int fwd_bands(int nw) { return nw <= 3 ? GPP_FWD_BANDS : (nw <= 4 ? 2 : 1); }
 // The same for the batched persistent forward's tiles, and the register cap
 // (minimum waves per SIMD) of its two-column form.  The batched kernel keeps
 // one column: with two, its persistent loop runs out of scalar registers,

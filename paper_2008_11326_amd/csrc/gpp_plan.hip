@@ -36,9 +36,19 @@ struct Candidate {
     int bu;       // bands per batch-inverted group
     int order;    // 0 = caller order, 1 = longest tiles first
     int sched;    // gpp::BatchedSchedule
-    int blocks;   // persistent workgroups (resident capacity)
-    long nchunks; // work-queue chunks (kSchedQueue)
+    int blocks;   // persistent workgroups (resident capacity); flat: all workgroups
+    long nchunks; // work-queue chunks (kSchedQueue); flat: workgroups
 };
+
+// Workgroups of the flat form for one state: its tiles of the plain
+// forward's shape, four per workgroup.
+long flat_workgroups(const gpp::Dims32 &d)
+{
+    if (!d.nb || !d.ng || !d.np) return 0;
+    const int cols = gpp::fwd_cols(d.nw);
+    const long tiles = (long)((d.ng + 63) / 64) * ((d.np + cols - 1) / cols);
+    return (tiles + 3) / 4;
+}
 
 // Tiles per work-queue chunk: small enough that the chunks in flight stay a
 // contiguous window of the tile list and the last chunks balance the end.
@@ -197,6 +207,7 @@ struct gpp_plan {
     std::string key;
     size_t ws_bytes = 0;
     int max_waves = 0;
+    bool forced = false;  // candidates restricted by GPP_BATCHED_SCHEDULE
     // descriptor table (nstates + 1 entries, then kXcdCount + 1 chunk
     // boundaries): device copy, pinned staging, event guarding reuse
     gpp::StateDesc *d_desc = nullptr, *h_desc = nullptr;
@@ -339,7 +350,10 @@ gpp_status upload(gpp_plan *pl, int cand, const gpp_inputs *in, hipStream_t st)
         o.out_index = s;
         o.pad = 0;
         tb += pl->tiles[s];
-        cb += (pl->tiles[s] + kQueueChunkTiles - 1) / kQueueChunkTiles;
+        // work-queue chunks, or for the flat form the state's workgroups
+        cb += pl->cands[cand].sched == gpp::kSchedFlat
+                  ? flat_workgroups(d)
+                  : (pl->tiles[s] + kQueueChunkTiles - 1) / kQueueChunkTiles;
     }
     memset(&pl->h_desc[pl->nstates], 0, sizeof(gpp::StateDesc));
     pl->h_desc[pl->nstates].tile_begin = tb;
@@ -379,7 +393,7 @@ hipError_t run(gpp_plan *pl, int c, double *ach, double *asx, void *ws, hipStrea
 gpp_status tune(gpp_plan *pl, const gpp_inputs *in, double *ach, double *asx, void *ws,
                 hipStream_t st)
 {
-    {
+    if (!pl->forced) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         load_cache_locked();
         auto it = g_cache.find(pl->key);
@@ -437,6 +451,7 @@ gpp_status tune(gpp_plan *pl, const gpp_inputs *in, double *ach, double *asx, vo
     t.order = pl->cands[best].order;
     t.sched = pl->cands[best].sched;
     t.ms = best_ms;
+    if (pl->forced) return GPP_OK;
     std::lock_guard<std::mutex> lk(g_cache_mu);
     store_cache_locked(pl->key, t);
     return GPP_OK;
@@ -540,17 +555,34 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
     else if (pl->nw <= 3) bus = {3, 2};
     else if (pl->nw == 4) bus = {2, 1};
     else bus = {1};
-    long nchunks = 0;
-    for (int s = 0; s < nstates; ++s)
+    long nchunks = 0, flat_wgs = 0;
+    for (int s = 0; s < nstates; ++s) {
         nchunks += (pl->tiles[s] + kQueueChunkTiles - 1) / kQueueChunkTiles;
+        flat_wgs += flat_workgroups(pl->dims[s]);
+    }
+    // GPP_BATCHED_SCHEDULE=<n> keeps only candidates of schedule n (tests);
+    // such a plan neither reads nor writes the tuning cache
+    int only = -1;
+    if (const char *f = getenv("GPP_BATCHED_SCHEDULE")) {
+        only = atoi(f);
+        pl->forced = true;
+    }
+    size_t rows = 0;
+    // the flat form first (the untuned default): the plain forward's tiles
+    // and registers, one workgroup per four tiles
+    if (flat_wgs <= 2147483647L && (only < 0 || only == gpp::kSchedFlat)) {
+        Candidate c{gpp::fwd_bands(pl->nw), 1, gpp::kSchedFlat, (int)flat_wgs, flat_wgs};
+        pl->cands.push_back(c);
+        rows = std::max(rows, (size_t)flat_wgs);
+    }
     // (schedule, order) pairs per tile variant; the queue ignores state order
     const int combos[4][2] = {{gpp::kSchedXcdQueues, 1},
                               {gpp::kSchedQueue, 1},
                               {gpp::kSchedXcdChunks, 1},
                               {gpp::kSchedRoundRobin, 1}};
-    size_t rows = 0;
     for (int bu : bus)
         for (const auto &cmb : combos) {
+            if (only >= 0 && cmb[0] != only) continue;
             int per_cu = 0;
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &per_cu, gpp::batched_kernel(pl->nw, bu, cmb[0]), 256, 0);
@@ -561,13 +593,18 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
             const bool queue = cmb[0] == gpp::kSchedQueue || cmb[0] == gpp::kSchedXcdQueues;
             rows = std::max(rows, queue ? (size_t)nchunks : (size_t)nstates * c.blocks * 4);
         }
+    if (pl->cands.empty()) {
+        delete pl;
+        return fail(GPP_ERR_INVALID, "GPP_BATCHED_SCHEDULE=%d matches no candidate", only);
+    }
     pl->ws_bytes = kPartialsOffset + (rows * 4 * pl->nw * sizeof(double) + 255) / 256 * 256;
 
     uint64_t h = fnv1a(&pl->nw, sizeof pl->nw);
     for (const auto &d : pl->dims) h = fnv1a(&d, sizeof d, h);
     char key[160];
-    snprintf(key, sizeof key, "gfx950:batched:nw=%d:cols=%d:n=%d:cus=%d:h=%016llx", pl->nw,
-             gpp::bat_cols(pl->nw), nstates, prop.multiProcessorCount, (unsigned long long)h);
+    snprintf(key, sizeof key, "gfx950:batched:nw=%d:cols=%d:s=%d:n=%d:cus=%d:h=%016llx", pl->nw,
+             gpp::bat_cols(pl->nw), gpp::kSchedCount, nstates, prop.multiProcessorCount,
+             (unsigned long long)h);
     pl->key = key;
 
     const size_t sbytes = sizeof(gpp::StateDesc) * (nstates + 1);

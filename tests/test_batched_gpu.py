@@ -58,6 +58,26 @@ def test_uneven_states_vs_oracle_and_plain(gpp, uneven, tmp_path, monkeypatch):
     plan.close()
 
 
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4])
+def test_every_schedule_vs_oracle(gpp, uneven, sched, monkeypatch):
+    """Each schedule alone (GPP_BATCHED_SCHEDULE): round-robin, XCD chunks,
+    global queue, per-XCD queues and the flat grid, on the uneven states
+    (including an empty one and a 1x1x1 one) against the oracle."""
+    import torch
+    monkeypatch.setenv("GPP_BATCHED_SCHEDULE", str(sched))
+    probs, refs, dev = uneven
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    ach, asx = gpp.sigma_batched(plan, dev)
+    torch.cuda.synchronize()
+    info = plan.info()
+    say(f"[batched] schedule {sched}: {info}")
+    assert info["schedule"] == sched and info["from_cache"] == 0
+    for k, ref in enumerate(refs):
+        assert_parity(ach[k].cpu().numpy(), ref[0], ref[2], f"state {k} achtemp")
+        assert_parity(asx[k].cpu().numpy(), ref[1], ref[3], f"state {k} asxtemp")
+    plan.close()
+
+
 def test_tiny_imaginary_lanes(gpp, tmp_path, monkeypatch):
     """States whose tiles mix lanes with (Im om)^2 below 2^-60 (one-by-one
     reciprocals, exact poles) with ordinary lanes, against the oracle."""

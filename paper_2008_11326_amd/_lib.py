@@ -10,7 +10,9 @@ import ctypes as C
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libgpp.so")
+# the in-tree build, or a variant build (paper_2008_11326_amd.build --out)
+# named by GPP_LIBRARY for measurements
+LIB_PATH = os.environ.get("GPP_LIBRARY") or os.path.join(PKG, "libgpp.so")
 
 GPP_OK = 0
 STATUS = {0: "GPP_OK", 1: "GPP_ERR_INVALID", 2: "GPP_ERR_HIP",

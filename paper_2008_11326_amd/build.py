@@ -1,6 +1,11 @@
 """Build libgpp.so (HIP, gfx950 only) in-tree.
 
     python -m paper_2008_11326_amd.build        # or build() from Python
+    python -m paper_2008_11326_amd.build --define GPP_FWD_COLS=1 --out /tmp/libgpp_c1.so
+
+The second form builds a variant with compile-time tuning knobs (the
+GPP_* macros the sources document) into a library of its own, for
+measurement; the package loads it when GPP_LIBRARY names it.
 
 Each .hip source compiles to an object with hipcc for gfx950, then they
 link into paper_2008_11326_amd/libgpp.so.  Packed-fp32 instructions are
@@ -31,9 +36,9 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, verbose: bool, objdir: str = OBJDIR, defines=()) -> str:
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,19 +52,23 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
     """Compile every HIP source for gfx950 and link libgpp.so (always
-    rebuilds)."""
-    os.makedirs(OBJDIR, exist_ok=True)
+    rebuilds).  With defines (NAME=VALUE strings) the objects go to a
+    directory of their own next to `out`, which must then be given too."""
+    if defines and os.path.abspath(out) == LIB:
+        raise ValueError("a variant build needs its own output path")
+    objdir = OBJDIR if not defines else os.path.splitext(os.path.abspath(out))[0] + "_obj"
+    os.makedirs(objdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, objdir, defines), SOURCES))
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 def is_stale() -> bool:
@@ -72,4 +81,9 @@ def is_stale() -> bool:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    import argparse
+    ap = argparse.ArgumentParser(description="build libgpp.so for gfx950")
+    ap.add_argument("--define", action="append", default=[], metavar="NAME=VALUE")
+    ap.add_argument("--out", default=LIB)
+    a = ap.parse_args()
+    build(verbose=True, defines=a.define, out=a.out)

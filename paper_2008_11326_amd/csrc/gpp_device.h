@@ -150,6 +150,13 @@ __device__ __forceinline__ void batch_reciprocal(const double (&d)[K], double (&
     }
 }
 
+// How the hot loops apply the branch-A test to a term.  1: as the wave's
+// execution mask around the term's accumulation (one compare, no select;
+// masked lanes add nothing); 0: through mask_keep on the reciprocal.
+#ifndef GPP_EXEC_MASK
+#define GPP_EXEC_MASK 1
+#endif
+
 // keep ? v : (a value of magnitude below 2^-1042) with one 32-bit select:
 // only the high word (sign, exponent, top mantissa bits) is cleared, which
 // leaves a denormal made of v's low word.  Added to any accumulator above

@@ -17,10 +17,12 @@
 // and ends with  achtemp += vcoul/2 * e * (om P1 - wtr P2).  The branch-A
 // test is one compare against a per-(p,g) threshold that reproduces the
 // specification exactly (gpp_device.h).  r = 1/wdiffr needs no IEEE divide
-// (the v1 idea); the BU*NW reciprocals of a group of BU bands come from a
-// single hardware reciprocal by batch inversion (gpp_device.h: unclamped
-// denominators, a lane test on (Im om)^2 for the product's range), and
-// masked terms clear the reciprocal's high word.  Occupied bands (n < nvband) also evaluate the
+// (the v1 idea); the 2*BU*NW reciprocals of a group of BU bands and both
+// columns come from a single hardware reciprocal by batch inversion
+// (gpp_device.h: unclamped denominators, a lane test on (Im om)^2 for the
+// product's range), and the branch-A test is the execution mask around
+// each term's four fused multiply-adds, so a masked term adds nothing and
+// costs no select.  Occupied bands (n < nvband) also evaluate the
 // screened-exchange term with full complex arithmetic.
 //
 // Each workgroup (4 waves) writes one partial per output into the

@@ -9,6 +9,11 @@
 #ifndef GPP_FWD_PREFETCH
 #define GPP_FWD_PREFETCH 0
 #endif
+// 1: the columns of a multi-column tile share one batch inversion per band
+// group; 0: one inversion per column.
+#ifndef GPP_FWD_JOINT_INV
+#define GPP_FWD_JOINT_INV 1
+#endif
 
 namespace gpp {
 
@@ -18,7 +23,8 @@ namespace gpp {
 // arithmetic stays on the scalar unit.  The denominators go into the batch
 // inversion unclamped: every one is at least (Im om)^2, and a lane with
 // (Im om)^2 below kMinUnclampedWi2 (wide == false) inverts one by one; a
-// masked term's reciprocal (possibly infinite or NaN there) is cleared.
+// masked term's reciprocal (possibly infinite or NaN there) never reaches
+// the sums (ch_term).
 // The group's aqsntemp values of this lane (one per band).
 template <int BU>
 __device__ __forceinline__ void load_an(int n, int ng, gptr<double2> aqsn, uint32_t goff,
@@ -26,6 +32,38 @@ __device__ __forceinline__ void load_an(int n, int ng, gptr<double2> aqsn, uint3
 {
 #pragma unroll
     for (int u = 0; u < BU; ++u) an[u] = load_row_elem(aqsn + (size_t)(n + u) * ng, ng, goff);
+}
+
+// an conj(am) for a lane's aqsntemp value and a wave-uniform aqsmtemp
+// value; the sign sits on the uniform factor, so it folds into an operand
+// modifier instead of costing a vector instruction.
+__device__ __forceinline__ cplx qm_of(cplx an, cplx am) {
+    const double nai = -am.im;
+    return cmake(fma(an.re, am.re, an.im * am.im), fma(an.im, am.re, an.re * nai));
+}
+
+// One Coulomb-hole term: P1 += r x qm and P2 += r qm when the term is on
+// branch A (isA).  With GPP_EXEC_MASK the test is the wave's execution mask
+// around the accumulation, laid out as the common case so that no skip
+// branch is emitted; otherwise the reciprocal is cleared with mask_keep.
+__device__ __forceinline__ void ch_term(bool isA, double r, double x, cplx qm, cplx &P1,
+                                        cplx &P2) {
+#if GPP_EXEC_MASK
+    if (__builtin_expect(isA, 1)) {
+        const double rx = r * x;
+        P1.re = fma(rx, qm.re, P1.re);
+        P1.im = fma(rx, qm.im, P1.im);
+        P2.re = fma(r, qm.re, P2.re);
+        P2.im = fma(r, qm.im, P2.im);
+    }
+#else
+    const double re = mask_keep(isA, r);
+    const double rx = re * x;
+    P1.re = fma(rx, qm.re, P1.re);
+    P1.im = fma(rx, qm.im, P1.im);
+    P2.re = fma(re, qm.re, P2.re);
+    P2.im = fma(re, qm.im, P2.im);
+#endif
 }
 
 template <int NW, int BU>
@@ -36,36 +74,70 @@ __device__ __forceinline__ void ch_group_an(int n, int nb, int ng, const cplx (&
 {
     constexpr int K = BU * NW;
     cplx qm[BU];
-    double xs[K], dc[K], r[K];
-    bool isA[K];
+    double xs[K], d[K], r[K];
 #pragma unroll
     for (int u = 0; u < BU; ++u) {
-        const cplx am = cload(am_col + (size_t)(n + u) * ng);
-        qm[u] = cmul_conj(an[u], am);
+        qm[u] = qm_of(an[u], cload(am_col + (size_t)(n + u) * ng));
 #pragma unroll
         for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double dr = xs[k] - a;
-        const double wd = fma(dr, dr, wi2);
-        isA[k] = wd > thr;
-        dc[k] = wd;
+        d[k] = fma(dr, dr, wi2);
     }
-    batch_reciprocal<K>(dc, r, wide);
+    batch_reciprocal<K>(d, r, wide);
 #pragma unroll
-    for (int u = 0; u < BU; ++u) {
+    for (int u = 0; u < BU; ++u)
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const int k = u * NW + w;
-            const double re = mask_keep(isA[k], r[k]);
-            const double rx = re * xs[k];
-            P1[w].re = fma(rx, qm[u].re, P1[w].re);
-            P1[w].im = fma(rx, qm[u].im, P1[w].im);
-            P2[w].re = fma(re, qm[u].re, P2[w].re);
-            P2[w].im = fma(re, qm[u].im, P2[w].im);
+            ch_term(d[k] > thr, r[k], xs[k], qm[u], P1[w], P2[w]);
+        }
+}
+
+// As ch_group_an for NC columns at once: the BU*NW*NC denominators of the
+// group share one batch inversion, which takes NC-1 fewer hardware
+// reciprocals and Newton steps for NC-1 more multiplies per link of the
+// prefix chain.  wide must hold for every column of the lane.
+template <int NW, int BU, int NC>
+__device__ __forceinline__ void ch_group_cols(int n, int nb, int ng, const cplx (&an)[BU],
+                                              gptr<double2> aqsm, const int (&pc)[NC],
+                                              gptr<double> wx, const double (&a)[NC],
+                                              const double (&wi2)[NC], const double (&thr)[NC],
+                                              bool wide, cplx (&P1)[NC][NW],
+                                              cplx (&P2)[NC][NW])
+{
+    constexpr int KB = BU * NW;  // terms of one column
+    constexpr int K = NC * KB;
+    double xs[KB], d[K], r[K];
+    cplx qm[NC][BU];
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            qm[c][u] = qm_of(an[u], cload(aqsm + pc[c] + (size_t)(n + u) * ng));
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const double dr = xs[k] - a[c];
+            d[c * KB + k] = fma(dr, dr, wi2[c]);
         }
     }
+    batch_reciprocal<K>(d, r, wide);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int u = 0; u < BU; ++u)
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int k = c * KB + u * NW + w;
+                ch_term(d[k] > thr[c], r[k], xs[u * NW + w], qm[c][u], P1[c][w], P2[c][w]);
+            }
 }
 
 template <int NW, int BU>
@@ -267,6 +339,21 @@ __device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int n
 
     // unoccupied bands: CH only
     int n = nv;
+#if GPP_FWD_JOINT_INV
+    bool wide_all = true;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) wide_all = wide_all && wide[c];
+    for (; n + BU <= nb; n += BU) {
+        cplx an[BU];
+        load_an<BU>(n, ng, aqsn, goff, an);
+        ch_group_cols<NW, BU, NC>(n, nb, ng, an, aqsm, pc, wx, a, wi2, thr, wide_all, P1, P2);
+    }
+    for (; n < nb; ++n) {
+        cplx an[1];
+        load_an<1>(n, ng, aqsn, goff, an);
+        ch_group_cols<NW, 1, NC>(n, nb, ng, an, aqsm, pc, wx, a, wi2, thr, wide_all, P1, P2);
+    }
+#else
     for (; n + BU <= nb; n += BU) {
         cplx an[BU];
         load_an<BU>(n, ng, aqsn, goff, an);
@@ -286,6 +373,7 @@ __device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int n
             ch_group_an<NW, 1>(n, nb, ng, an, aqsm + pc[c], wx, a[c], wi2[c], thr[c], wide[c],
                                P1[c], P2[c]);
     }
+#endif
 
 #pragma unroll
     for (int w = 0; w < NW; ++w) ach[w] = cmake(0.0, 0.0);

@@ -42,7 +42,7 @@ constexpr int kFwdThreads = kFwdWaves * kWave;
 // fwd_cols and fwd_bands (gpp_internal.h), and an optional cap on VGPRs
 // through a minimum number of waves per SIMD; chosen by measurement on
 // MI355X.  Two columns per wave let each aqsntemp load
-// serve both: 148 VGPRs (3 waves per SIMD) at nfreq 3 with 2-band groups,
+// serve both: 153 VGPRs (3 waves per SIMD) at nfreq 3 with 2-band groups,
 // 2.8-3.1 % faster than one column with 3-band groups (105 VGPRs, 4 waves).
 // Three columns need about 200 VGPRs (2 waves) and measured 3-30 % slower.
 // With 4 or more frequencies a second column would leave 2 waves or fewer,

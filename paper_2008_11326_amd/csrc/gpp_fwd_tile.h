@@ -6,9 +6,6 @@
 
 #include "gpp_device.h"
 
-#ifndef GPP_FWD_PREFETCH
-#define GPP_FWD_PREFETCH 0
-#endif
 // 1: the columns of a multi-column tile share one batch inversion per band
 // group; 0: one inversion per column.
 #ifndef GPP_FWD_JOINT_INV
@@ -241,24 +238,8 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
     // unoccupied bands: CH only -- the hot loop
     const bool wide = wi2 >= kMinUnclampedWi2;
     int n = nv;
-#if GPP_FWD_PREFETCH
-    // the next group's aqsntemp values are loaded while this group computes
-    // (the last group reloads its own rows, so every load stays in range)
-    if (n + BU <= nb) {
-        cplx an[BU];
-        load_an<BU>(n, ng, aqsn, goff, an);
-        for (; n + BU <= nb; n += BU) {
-            cplx an_next[BU];
-            load_an<BU>(n + 2 * BU <= nb ? n + BU : n, ng, aqsn, goff, an_next);
-            ch_group_an<NW, BU>(n, nb, ng, an, am_col, wx, a, wi2, thr, wide, P1, P2);
-#pragma unroll
-            for (int u = 0; u < BU; ++u) an[u] = an_next[u];
-        }
-    }
-#else
     for (; n + BU <= nb; n += BU)
         ch_group<NW, BU>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
-#endif
     for (; n < nb; ++n)
         ch_group<NW, 1>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
 

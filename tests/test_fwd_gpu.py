@@ -103,6 +103,29 @@ def test_tiny_imaginary_lanes_and_exact_poles(gpp, frac):
     check(gpp, prob, f"tiny-Im lanes {frac}", nthreads=1)
 
 
+@pytest.mark.parametrize("nw", [3, 5])
+def test_every_term_masked_gives_exact_zero(gpp, nw):
+    """No occupied bands and every |x - om|^2 at or below 1/4, so no term is
+    on branch A: achtemp and asxtemp are exactly zero in the oracle, and the
+    kernels, which leave masked terms out of the sums, must return exact
+    zeros too -- also for lanes with real om on an exact pole (x == om, an
+    infinite reciprocal that must never reach a sum).  nfreq 3 runs the
+    two-column tiles, nfreq 5 the one-column tiles."""
+    prob = _tile_edge_problem(50 + nw, 9, 0, 200, 7, nw)
+    rng = np.random.default_rng(nw)
+    prob.wx_array[:] = 1.0
+    wt = 1.0 + rng.uniform(-0.3, 0.3, prob.wtilde_array.shape) \
+        + 1j * rng.uniform(-0.3, 0.3, prob.wtilde_array.shape)
+    pole = rng.random(wt.shape) < 0.1
+    wt[pole] = 1.0
+    prob.wtilde_array = wt
+    ref = oracle.sigma_fwd(prob, nthreads=1)
+    assert np.all(ref[0] == 0) and np.all(ref[1] == 0)
+    say(f"[fwd] every term masked, nfreq {nw}")
+    ach, asx = run(gpp, prob)
+    assert np.all(ach == 0) and np.all(asx == 0), (ach, asx)
+
+
 def test_empty_dimensions(gpp):
     for dims in (I.Dims(0, 0, 64, 4, 3), I.Dims(4, 1, 64, 0, 3),
                  I.Dims(4, 1, 0, 0, 2)):

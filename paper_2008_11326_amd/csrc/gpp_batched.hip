@@ -246,8 +246,8 @@ batched_flat(const StateDesc *__restrict__ st, int nstates, double *__restrict__
 #pragma unroll
     for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
     if (local < ntile) {
-        const int gt = (int)(local / npt);
-        const int pt = (int)(local - (long)gt * npt);
+        int gt, pt;
+        tile_coords(local, npt, (d.ng + kWave - 1) / kWave, gt, pt);
         if (C == 1) {
             fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, pt, gt, lane, as_global(d.aqsm),
                                   as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),

@@ -75,8 +75,8 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
         // consecutive tiles share a g-tile (and so the same aqsntemp rows)
         constexpr int C = fwd_cols(NW);
         const int npt = (np + C - 1) / C;  // column tiles per g-tile
-        const int gt = (int)(tile / npt);
-        const int pt = (int)(tile - (long)gt * npt);
+        int gt, pt;
+        tile_coords(tile, npt, (ng + kWave - 1) / kWave, gt, pt);
         if (C == 1) {
             fwd_tile_body<NW, BU>(nb, nv, ng, pt, gt, lane, as_global(aqsm), as_global(aqsn),
                                   as_global(ieps), as_global(wt), as_global(vcoul),

@@ -71,6 +71,8 @@ def _tile_edge_problem(seed, nb, nv, ng, npw, nw, poles=0.0):
     (7, 7, 200, 9, 3), (1, 1, 130, 1, 3), (1, 0, 1, 1, 3), (40, 3, 777, 13, 3),
     (3, 1, 129, 5, 1), (3, 1, 129, 5, 2), (3, 1, 129, 5, 4), (3, 1, 129, 5, 5),
     (3, 1, 129, 5, 6), (3, 1, 129, 5, 7), (3, 1, 129, 5, 8),
+    # several blocks of the tile walk (64 column tiles each) with a short last one
+    (6, 1, 321, 300, 3), (4, 1, 321, 150, 5),
 ])
 def test_ragged_and_nfreq(gpp, shape):
     prob = _tile_edge_problem(sum(shape), *shape)

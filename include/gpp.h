@@ -99,9 +99,9 @@ size_t gpp_sigma_fwd_workspace(const gpp_dims *dims);
  * Three kernels run on `stream`: the tile kernel writes one partial per
  * workgroup into the workspace, then two fixed-order reduction stages
  * produce the outputs (the separate reduction kernel of Sec. II-A).
- * Masked (branch B/C) Coulomb-hole terms contribute below 2^-1000 in
- * absolute value, so an output whose exact value is 0 comes back with
- * magnitude below 1e-300.
+ * Masked (branch B/C) Coulomb-hole terms add nothing to the sums (the
+ * branch test is the execution mask of their accumulation), so an output
+ * none of whose terms is on branch A comes back exactly 0.
  */
 gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
                          double *achtemp, double *asxtemp, void *workspace,

@@ -150,11 +150,13 @@ __device__ __forceinline__ void batch_reciprocal(const double (&d)[K], double (&
     }
 }
 
-// How the hot loops apply the branch-A test to a term.  1: as the wave's
-// execution mask around the term's accumulation (one compare, no select;
-// masked lanes add nothing); 0: through mask_keep on the reciprocal.
+// How the hot loops apply the branch-A test to a term.  2: the compare
+// itself writes the wave's execution mask (v_cmpx) around the term's
+// accumulation; 1: the same mask through a compiler-generated branch (a
+// compare, then a scalar mask update); in both, masked lanes add nothing
+// and no select is spent.  0: through mask_keep on the reciprocal.
 #ifndef GPP_EXEC_MASK
-#define GPP_EXEC_MASK 1
+#define GPP_EXEC_MASK 2
 #endif
 
 // keep ? v : (a value of magnitude below 2^-1042) with one 32-bit select:

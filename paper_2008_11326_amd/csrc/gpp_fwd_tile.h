@@ -92,6 +92,34 @@ __device__ __forceinline__ void ch_term(bool isA, double r, double x, cplx qm, c
 #endif
 }
 
+// ch_term on the denominator d against the branch-A threshold thr.  With
+// GPP_EXEC_MASK == 2 the compare writes the execution mask itself
+// (v_cmpx), so the term's five vector instructions wait on one vector
+// result instead of a compare, a scalar mask update and the exec write;
+// the mask is restored before the block ends.
+__device__ __forceinline__ void ch_term_dt(double d, double thr, double r, double x, cplx qm,
+                                           cplx &P1, cplx &P2) {
+#if GPP_EXEC_MASK == 2
+    unsigned long long saved;
+    double rx;
+    asm volatile(
+        "s_mov_b64 %[sv], exec\n\t"
+        "v_cmpx_gt_f64_e32 vcc, %[d], %[thr]\n\t"
+        "v_mul_f64 %[rx], %[r], %[x]\n\t"
+        "v_fma_f64 %[p2r], %[r], %[qr], %[p2r]\n\t"
+        "v_fma_f64 %[p2i], %[r], %[qi], %[p2i]\n\t"
+        "v_fma_f64 %[p1r], %[rx], %[qr], %[p1r]\n\t"
+        "v_fma_f64 %[p1i], %[rx], %[qi], %[p1i]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [sv] "=&s"(saved), [rx] "=&v"(rx), [p1r] "+v"(P1.re), [p1i] "+v"(P1.im),
+          [p2r] "+v"(P2.re), [p2i] "+v"(P2.im)
+        : [d] "v"(d), [thr] "v"(thr), [r] "v"(r), [x] "s"(x), [qr] "v"(qm.re), [qi] "v"(qm.im)
+        : "vcc");
+#else
+    ch_term(d > thr, r, x, qm, P1, P2);
+#endif
+}
+
 template <int NW, int BU>
 __device__ __forceinline__ void ch_group_an(int n, int nb, int ng, const cplx (&an)[BU],
                                             gptr<double2> am_col, gptr<double> wx, double a,
@@ -118,7 +146,7 @@ __device__ __forceinline__ void ch_group_an(int n, int nb, int ng, const cplx (&
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const int k = u * NW + w;
-            ch_term(d[k] > thr, r[k], xs[k], qm[u], P1[w], P2[w]);
+            ch_term_dt(d[k], thr, r[k], xs[k], qm[u], P1[w], P2[w]);
         }
 }
 
@@ -162,7 +190,7 @@ __device__ __forceinline__ void ch_group_cols(int n, int nb, int ng, const cplx 
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 const int k = c * KB + u * NW + w;
-                ch_term(d[k] > thr[c], r[k], xs[u * NW + w], qm[c][u], P1[c][w], P2[c][w]);
+                ch_term_dt(d[k], thr[c], r[k], xs[u * NW + w], qm[c][u], P1[c][w], P2[c][w]);
             }
 }
 

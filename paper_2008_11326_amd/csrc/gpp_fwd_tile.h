@@ -25,6 +25,9 @@ namespace gpp {
 #endif
 
 // (g-tile, column tile) of a tile index, a bijection on [0, gtiles * npt).
+// The tile is wave-uniform; the results are made scalar explicitly, since
+// the divisions run on the vector unit and a column index left in vector
+// registers would turn the tile's aqsmtemp loads into vector loads.
 __device__ inline void tile_coords(long tile, int npt, int gtiles, int &gt, int &pt)
 {
 #if GPP_FWD_COL_BLOCK > 0
@@ -41,6 +44,8 @@ __device__ inline void tile_coords(long tile, int npt, int gtiles, int &gt, int 
     gt = (int)(tile / npt);
     pt = (int)(tile - (long)gt * npt);
 #endif
+    gt = __builtin_amdgcn_readfirstlane(gt);
+    pt = __builtin_amdgcn_readfirstlane(pt);
 }
 
 // CH-only accumulation for BU consecutive unoccupied bands starting at n.

@@ -101,10 +101,7 @@ __device__ __forceinline__ void ch_term(bool isA, double r, double x, cplx qm, c
 // GPP_EXEC_MASK == 2 the compare writes the execution mask itself
 // (v_cmpx), so the term's five vector instructions wait on one vector
 // result instead of a compare, a scalar mask update and the exec write;
-// the mask is restored before the block ends.  Used by the multi-column
-// tiles only: in the one-column tile the compiler keeps wx in vector
-// registers and the block's scalar operand then costs a readfirstlane pair
-// per term (8 % more instructions).
+// the mask is restored before the block ends.
 __device__ __forceinline__ void ch_term_dt(double d, double thr, double r, double x, cplx qm,
                                            cplx &P1, cplx &P2) {
 #if GPP_EXEC_MASK == 2
@@ -154,7 +151,7 @@ __device__ __forceinline__ void ch_group_an(int n, int nb, int ng, const cplx (&
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const int k = u * NW + w;
-            ch_term(d[k] > thr, r[k], xs[k], qm[u], P1[w], P2[w]);
+            ch_term_dt(d[k], thr, r[k], xs[k], qm[u], P1[w], P2[w]);
         }
 }
 

@@ -18,14 +18,6 @@
 // in a fixed order.  Waves never wait on each other, so the grid needs no
 // co-residency and every wave reaches its exit.  The per-tile arithmetic is
 // the plain forward's (gpp_fwd_tile.h).
-//
-// These kernels apply branch A through the compiler's masked branch
-// (GPP_EXEC_MASK 1) unless the build sets the form: with the v_cmpx form the
-// flat grid's two-column tile needs 182 VGPRs (2 waves per SIMD) and ran
-// 15 % slower.
-#ifndef GPP_EXEC_MASK
-#define GPP_EXEC_MASK 1
-#endif
 #include "gpp_device.h"
 #include "gpp_fwd_tile.h"
 #include "gpp_internal.h"

@@ -107,7 +107,10 @@ __device__ __forceinline__ void ch_term_dt(double d, double thr, double r, doubl
 #if GPP_EXEC_MASK == 2
     unsigned long long saved;
     double rx;
-    asm volatile(
+    // Not volatile: the block touches no memory and restores exec, and a
+    // volatile block would count as a possible store, which keeps the
+    // compiler from turning later wave-uniform loads into scalar loads.
+    asm(
         "s_mov_b64 %[sv], exec\n\t"
         "v_cmpx_gt_f64_e32 vcc, %[d], %[thr]\n\t"
         "v_mul_f64 %[rx], %[r], %[x]\n\t"

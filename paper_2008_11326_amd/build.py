@@ -1,7 +1,7 @@
 """Build libgpp.so (HIP, gfx950 only) in-tree.
 
     python -m paper_2008_11326_amd.build        # or build() from Python
-    python -m paper_2008_11326_amd.build --define GPP_FWD_COLS=1 --out /tmp/libgpp_c1.so
+    python -m paper_2008_11326_amd.build --define GPP_FWD_COLS=1 --out $VDIR/libgpp_c1.so
 
 The second form builds a variant with compile-time tuning knobs (the
 GPP_* macros the sources document) into a library of its own, for

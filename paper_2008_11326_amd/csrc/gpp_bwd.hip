@@ -189,13 +189,13 @@ __device__ __forceinline__ void sx_band_kl(int n, int nb, const double *__restri
 
 // Batch-inverted reciprocals of the BU*NW terms of BU bands starting at
 // band n for one lane, masked to branch A, and dr = x - Re om.
-template <int NW, int BU>
+template <int NW, int BU, bool MASK = true>
 __device__ __forceinline__ void group_reciprocals(int n, int nb, const double *__restrict__ wx,
                                                   double a, double wi2, double thr, bool wide,
-                                                  double (&r)[BU * NW], double (&drs)[BU * NW])
+                                                  double (&r)[BU * NW], double (&drs)[BU * NW],
+                                                  double (&dc)[BU * NW])
 {
     constexpr int Kt = BU * NW;
-    double dc[Kt];
     bool isA[Kt];
 #pragma unroll
     for (int u = 0; u < BU; ++u)
@@ -208,8 +208,10 @@ __device__ __forceinline__ void group_reciprocals(int n, int nb, const double *_
         dc[k] = wd;  // unclamped: see batch_reciprocal
     }
     batch_reciprocal<Kt>(dc, r, wide);
+    if (MASK) {
 #pragma unroll
-    for (int k = 0; k < Kt; ++k) r[k] = mask_keep(isA[k], r[k]);
+        for (int k = 0; k < Kt; ++k) r[k] = mask_keep(isA[k], r[k]);
+    }
 }
 
 struct PairState {
@@ -291,10 +293,10 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
 #pragma unroll 1
                 for (int q0 = 0; q0 < kSlab; q0 += kBwdGroup) {
                     constexpr int Kt = kBwdGroup * NW;
-                    double r[Kt], drs[Kt];
+                    double r[Kt], drs[Kt], dcs[Kt];
                     const int ng0 = opaque_uniform(__builtin_amdgcn_readfirstlane(b0 + q0));
-                    group_reciprocals<NW, kBwdGroup>(ng0, nb, wx, ps.a, ps.wi2, ps.thr,
-                                                     ps.wide, r, drs);
+                    group_reciprocals<NW, kBwdGroup, GPP_EXEC_MASK != 2>(
+                        ng0, nb, wx, ps.a, ps.wi2, ps.thr, ps.wide, r, drs, dcs);
 #pragma unroll
                     for (int u = 0; u < kBwdGroup; ++u) {
                         const int nn = ng0 + u;
@@ -302,10 +304,42 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
 #pragma unroll
                         for (int w = 0; w < NW; ++w) {
                             const int k = u * NW + w;
-                            const double q = r[k] * r[k];
-                            const double dq = drs[k] * q;
                             const cplx g = cload(gh + w);
                             const cplx xg = cload(xgh + (size_t)w * nb + nn);
+#if GPP_EXEC_MASK == 2
+                            if (w > 0) {
+                                // later frequencies add under an execution
+                                // mask written by the branch-A compare
+                                unsigned long long saved;
+                                double q, dq;
+                                asm("s_mov_b64 %[sv], exec\n\t"
+                                    "v_cmpx_gt_f64_e32 vcc, %[d], %[thr]\n\t"
+                                    "v_mul_f64 %[q], %[r], %[r]\n\t"
+                                    "v_fma_f64 %[sr], %[r], %[xr], %[sr]\n\t"
+                                    "v_fma_f64 %[si], %[r], %[xi], %[si]\n\t"
+                                    "v_fma_f64 %[rr], %[r], %[gr], %[rr]\n\t"
+                                    "v_fma_f64 %[ri], %[r], %[gi], %[ri]\n\t"
+                                    "v_mul_f64 %[dq], %[dr], %[q]\n\t"
+                                    "v_fma_f64 %[tr], %[q], %[xr], %[tr]\n\t"
+                                    "v_fma_f64 %[ti], %[q], %[xi], %[ti]\n\t"
+                                    "v_fma_f64 %[ur], %[dq], %[xr], %[ur]\n\t"
+                                    "v_fma_f64 %[ui], %[dq], %[xi], %[ui]\n\t"
+                                    "s_mov_b64 exec, %[sv]"
+                                    : [sv] "=&s"(saved), [q] "=&v"(q), [dq] "=&v"(dq),
+                                      [sr] "+v"(S.re), [si] "+v"(S.im), [rr] "+v"(R.re),
+                                      [ri] "+v"(R.im), [tr] "+v"(T.re), [ti] "+v"(T.im),
+                                      [ur] "+v"(U.re), [ui] "+v"(U.im)
+                                    : [d] "v"(dcs[k]), [thr] "v"(ps.thr), [r] "v"(r[k]),
+                                      [dr] "v"(drs[k]), [xr] "s"(xg.re), [xi] "s"(xg.im),
+                                      [gr] "s"(g.re), [gi] "s"(g.im)
+                                    : "vcc");
+                                continue;
+                            }
+                            // the first frequency starts the sums through a select
+                            r[k] = mask_keep(dcs[k] > ps.thr, r[k]);
+#endif
+                            const double q = r[k] * r[k];
+                            const double dq = drs[k] * q;
                             S.re = fma(r[k], xg.re, S.re);
                             S.im = fma(r[k], xg.im, S.im);
                             R.re = fma(r[k], g.re, R.re);
@@ -477,6 +511,33 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
             batch_reciprocal<Kt>(dc, r, wide);
 #pragma unroll
             for (int u = 0; u < kBwdGroup; ++u) {
+#if GPP_EXEC_MASK == 2
+                // the first frequency starts S and R through a select, the
+                // others add under an execution mask written by the compare
+                const double r0 = mask_keep(isA[u * NW], r[u * NW]);
+                const cplx xg0 = cload(xgh + n + u);
+                const cplx g0 = cload(gh);
+                cplx S = cmake(r0 * xg0.re, r0 * xg0.im), R = cmake(r0 * g0.re, r0 * g0.im);
+#pragma unroll
+                for (int w = 1; w < NW; ++w) {
+                    const int k = u * NW + w;
+                    const cplx xg = cload(xgh + (size_t)w * nb + n + u);
+                    const cplx g = cload(gh + w);
+                    unsigned long long saved;
+                    asm("s_mov_b64 %[sv], exec\n\t"
+                        "v_cmpx_gt_f64_e32 vcc, %[d], %[thr]\n\t"
+                        "v_fma_f64 %[sr], %[r], %[xr], %[sr]\n\t"
+                        "v_fma_f64 %[si], %[r], %[xi], %[si]\n\t"
+                        "v_fma_f64 %[rr], %[r], %[gr], %[rr]\n\t"
+                        "v_fma_f64 %[ri], %[r], %[gi], %[ri]\n\t"
+                        "s_mov_b64 exec, %[sv]"
+                        : [sv] "=&s"(saved), [sr] "+v"(S.re), [si] "+v"(S.im), [rr] "+v"(R.re),
+                          [ri] "+v"(R.im)
+                        : [d] "v"(dc[k]), [thr] "v"(thr), [r] "v"(r[k]), [xr] "s"(xg.re),
+                          [xi] "s"(xg.im), [gr] "s"(g.re), [gi] "s"(g.im)
+                        : "vcc");
+                }
+#else
                 cplx S = cmake(0.0, 0.0), R = cmake(0.0, 0.0);
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
@@ -489,6 +550,7 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
                     R.re = fma(re, g.re, R.re);
                     R.im = fma(re, g.im, R.im);
                 }
+#endif
                 const cplx vZ = cmake(c1.re * S.re - c1.im * S.im - c2.re * R.re + c2.im * R.im,
                                       c1.re * S.im + c1.im * S.re - c2.re * R.im - c2.im * R.re);
                 const cplx am = cload(aqsm + (size_t)(n + u) * ng + p);

@@ -188,7 +188,9 @@ __device__ __forceinline__ void sx_band_kl(int n, int nb, const double *__restri
 }
 
 // Batch-inverted reciprocals of the BU*NW terms of BU bands starting at
-// band n for one lane, masked to branch A, and dr = x - Re om.
+// band n for one lane, dr = x - Re om and the denominators dc.  With MASK
+// the reciprocals of terms off branch A are cleared (mask_keep); without
+// it the caller applies the branch itself (dc against the threshold).
 template <int NW, int BU, bool MASK = true>
 __device__ __forceinline__ void group_reciprocals(int n, int nb, const double *__restrict__ wx,
                                                   double a, double wi2, double thr, bool wide,

@@ -3,22 +3,31 @@
 one MI355X.
 
 A step is one gpp_sigma_fwd call (tile kernel + fixed-order reduction
-kernel) over the synthetic workload with the per-task shape of the paper's
-Si-system run: number_bands=512, nvband=2, ncouls=32768, ngpown=1638,
-nfreq=3, inputs resident in HBM.  Prints one JSON line on stdout.
+kernels) over the larger synthetic system: number_bands=1024, nvband=4,
+ncouls=65536, ngpown=3276, nfreq=3, 1 % of wtilde planted within 1e-6 of a
+frequency, seed 2; inputs resident in HBM.  Prints one JSON line on stdout.
 
-    python bench.py [--steps K] [--warmup W] [--workload si|small|adjoint|large]
-    python bench.py --leg adjoint|batched     # one leg alone, for profiling
+    python bench.py [--steps K] [--warmup W] [--workload large|si|small|adjoint]
+    python bench.py --leg adjoint|batched|si     # one leg alone, for profiling
 
-Throughput is algorithmic: 21 fp64 operations per Coulomb-hole term plus
-21 per screened-exchange term (the arithmetic the method needs, fixed
-independently of the implementation), divided by the measured time.  The
-roofline block compares it with the MI355X fp64 vector-ALU peak.  The CPU
-baseline times the plain oracle on a bounded slice of the same workload.
+`value` is the fp64 FLOP rate the hardware counts (the paper's measure,
+Eq. 2): the fp64 VALU instructions of the tile kernel, counted once with
+rocprofv3 for the same sources and workload (profiles/gpp_fwd_tiles_*.json,
+keyed by a digest of the forward sources), divided by the time measured
+here.  Beside it: the algorithmic rate (21 fp64 operations per Coulomb-hole
+and per screened-exchange term, fixed by the method), the FMA-share
+ceiling of Sec. III (the closing FMA-ratio paragraph), the share of the
+fp64 FMA rate a microbenchmark reaches on this GPU, and the Si-shaped
+workload's rate.  The roofline block compares the algorithmic rate of the
+tile kernel with the MI355X fp64 vector-ALU peak.  The CPU baseline times
+the plain oracle on a bounded slice of the same workload.
 """
 import argparse
+import ctypes as C
+import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -29,6 +38,7 @@ if ROOT not in sys.path:
 METRIC = "GPP FP64 TFLOP/s and % FP64 peak; batched/adjoint vs plain at 1e-12 rel"
 FLOP_PER_TERM = 21
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 fp64 FLOP/clk/CU
+FWD_SOURCES = ("gpp_fwd.hip", "gpp_fwd_tile.h", "gpp_device.h")
 
 
 def log(msg):
@@ -36,26 +46,36 @@ def log(msg):
 
 
 def fwd_source_digest():
-    import hashlib
     h = hashlib.sha256()
-    for f in ("gpp_fwd.hip", "gpp_fwd_tile.h", "gpp_device.h"):
+    for f in FWD_SOURCES:
         with open(os.path.join(ROOT, "paper_2008_11326_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name):
-    """HBM-side bytes per launch from the committed counter run
-    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
-    copy of known size), or None when the kernel sources changed since."""
+def kernel_counters(workload_name):
+    """The committed counter record of the tile kernel on this workload
+    (rocprofv3 --pmc passes over the same sources), or None when the
+    forward sources changed since the counters were taken."""
     import glob
-    for path in glob.glob(os.path.join(ROOT, "profiles", "gpp_fwd_tiles_*.json")):
+    digest = fwd_source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "gpp_fwd_tiles_*.json"))):
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("workload") == workload_name and \
-                rec.get("source_digest") == fwd_source_digest():
-            return rec["traffic_bytes"]
+        if rec.get("workload") == workload_name and rec.get("source_digest") == digest:
+            rec["path"] = os.path.relpath(path, ROOT)
+            return rec
     return None
+
+
+def counted_fp64(rec):
+    """fp64 operations the hardware counts per launch (64 lanes per wave
+    instruction, an FMA counts 2) and the FMA share of the fp64 add, multiply
+    and FMA instructions, from a counter record."""
+    v = rec["valu_f64"]
+    flops = 64.0 * (v["add"] + v["mul"] + v["trans"] + 2.0 * v["fma"])
+    fma_share = v["fma"] / (v["add"] + v["mul"] + v["fma"])
+    return flops, fma_share
 
 
 def cpu_baseline(prob, target_seconds):
@@ -92,14 +112,37 @@ def cpu_baseline(prob, target_seconds):
 
 
 def _cpu_model():
+    """lscpu's model name, with vendor, family/model/stepping and hypervisor
+    (a virtual machine may report only a generic name)."""
+    fields = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return None
+    if not fields.get("Model name"):
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        fields["Model name"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    name = fields.get("Model name")
+    if not name:
+        return None
+    extra = [fields.get("Vendor ID")]
+    if fields.get("CPU family"):
+        extra.append(f"family {fields['CPU family']} model {fields.get('Model')} "
+                     f"stepping {fields.get('Stepping')}")
+    if fields.get("Hypervisor vendor"):
+        extra.append(f"{fields['Hypervisor vendor']} guest")
+    extra = [e for e in extra if e]
+    return name + (f" ({', '.join(extra)})" if extra else "")
 
 
 def timed_ms(fn, stream, reps):
@@ -115,6 +158,110 @@ def timed_ms(fn, stream, reps):
     b.record(stream)
     torch.cuda.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def fwd_leg(gpp, I, key, steps, warmup, stream):
+    """Time `steps` gpp_sigma_fwd calls on workload `key` after `warmup`
+    untimed ones: events on the launch stream around the whole run and
+    around every call.  Returns (numbers, Problem, outputs)."""
+    import numpy as np
+    import torch
+    wl = I.WORKLOADS[key]
+    d = wl.dims
+    log(f"[bench] generating {wl.name}")
+    t0 = time.perf_counter()
+    prob = I.make_problem(d, wl.seed, wl.pole_fraction)
+    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    t_in = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in prob.arrays()]
+    ach = torch.empty(d.nfreq, dtype=torch.complex128, device=dev)
+    asx = torch.empty(d.nfreq, dtype=torch.complex128, device=dev)
+    ws = torch.empty(gpp.fwd_workspace_bytes(*d.as_tuple()), dtype=torch.uint8, device=dev)
+
+    def step():
+        gpp.sigma_fwd(*t_in, nvband=d.nvband, out=(ach, asx), workspace=ws,
+                      stream=stream.cuda_stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_all0.record(stream)
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_all0.elapsed_time(t_all1)
+    per_launch = [a.elapsed_time(b) for a, b in ev]
+    log(f"[bench] {wl.name}: {steps} steps {total_ms:.3f} ms on device, "
+        f"{wall * 1e3:.3f} ms wall; per call min {min(per_launch):.3f} "
+        f"max {max(per_launch):.3f} ms")
+    res = (ach.cpu().numpy(), asx.cpu().numpy())
+    del t_in, ws, ach, asx
+    torch.cuda.empty_cache()
+    return {"workload": wl, "ms_per_step": total_ms / steps,
+            "launch_ms": sum(per_launch) / len(per_launch),
+            "launch_ms_min": min(per_launch), "launch_ms_max": max(per_launch)}, prob, res
+
+
+def rates(wl, launch_ms, ms_per_step):
+    """Algorithmic and (where the committed counters match) counted rates."""
+    d = wl.dims
+    terms = d.ch_terms + d.sx_terms
+    alg = FLOP_PER_TERM * terms
+    out = {"terms": terms, "algorithmic_tflops": alg / (ms_per_step * 1e-3) / 1e12,
+           "algorithmic_tflops_launch": alg / (launch_ms * 1e-3) / 1e12,
+           "terms_per_s": terms / (ms_per_step * 1e-3)}
+    rec = kernel_counters(wl.name)
+    if rec is not None and "valu_f64" in rec:
+        flops, f = counted_fp64(rec)
+        ceiling = (2.0 * f + (1.0 - f)) / 2.0 * FP64_VECTOR_PEAK_TFLOPS
+        out.update({
+            "counted_tflops": flops / (ms_per_step * 1e-3) / 1e12,
+            "counted_flops_per_launch": flops, "fma_share": f,
+            "fma_ceiling_tflops": ceiling, "counters": rec["path"],
+            "traffic": rec.get("traffic_bytes"),
+        })
+    elif rec is not None:
+        out["traffic"] = rec.get("traffic_bytes")
+    return out
+
+
+def max_rel_err(key, res):
+    from tests.gpu_helpers import load_golden, rel_errors
+    gold = load_golden(key)
+    if gold is None:
+        return None
+    return float(max(rel_errors(res[0], gold["ach"], gold["ach_abs_sum"]).max(),
+                     rel_errors(res[1], gold["asx"], gold["asx_abs_sum"]).max()))
+
+
+def fma_peak_leg(stream, reps=5):
+    """fp64 FMA rate of the microbenchmark kernel (16 independent chains per
+    lane, 8 waves per SIMD) on this GPU, best of `reps`."""
+    import torch
+    from paper_2008_11326_amd import _lib
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks = cus * 8
+    out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+    flops = C.c_double(0.0)
+
+    def run():
+        _lib.check(lib.gpp_mb_fp64_fma(C.c_void_p(out.data_ptr()), blocks, 4096,
+                                       C.c_void_p(stream.cuda_stream), C.byref(flops)),
+                   "gpp_mb_fp64_fma")
+    best = min(timed_ms(run, stream, 1) for _ in range(reps))
+    return flops.value / (best * 1e-3) / 1e12
 
 
 def adjoint_leg(gpp, I, stream, reps=5):
@@ -179,7 +326,23 @@ def batched_leg(gpp, I, stream, reps=3):
             "max_rel_diff_vs_plain": worst,
             "plan": {k: info[k] for k in ("bands_per_group", "schedule_order", "schedule",
                                            "waves", "candidates", "from_cache")},
-            "data": "synthetic, drawn on the device (same distributions)"}
+            "data": "synthetic: the 64 state sizes of the seed-3 batched workload, values "
+                    "drawn on the device from the same distributions with torch's "
+                    "generator, seed 1000+s for state s (not the seed-3 host values)"}
+
+
+def si_leg(gpp, I, stream, steps=5, warmup=2):
+    """The Si-shaped per-task workload (512 bands, 32768 rows, 1638 columns)."""
+    r, _, res = fwd_leg(gpp, I, "si", steps, warmup, stream)
+    wl = r["workload"]
+    q = rates(wl, r["launch_ms"], r["ms_per_step"])
+    out = {"workload": wl.name, "ms_per_step": round(r["ms_per_step"], 4),
+           "algorithmic_tflops": round(q["algorithmic_tflops"], 4),
+           "terms_per_s": q["terms_per_s"], "max_rel_err_vs_oracle": max_rel_err("si", res)}
+    if "counted_tflops" in q:
+        out["counted_tflops"] = round(q["counted_tflops"], 4)
+        out["fma_share"] = round(q["fma_share"], 4)
+    return out
 
 
 def main():
@@ -187,13 +350,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="si")
+    ap.add_argument("--workload", default="large")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the adjoint and batched legs")
-    ap.add_argument("--leg", choices=("all", "adjoint", "batched"), default="all",
-                    help="adjoint or batched: run only that leg and print its JSON "
+                    help="skip the Si-shaped, adjoint, batched and FMA-peak legs")
+    ap.add_argument("--leg", choices=("all", "adjoint", "batched", "si"), default="all",
+                    help="adjoint, batched or si: run only that leg and print its JSON "
                          "(for per-kernel profiling); all: the benchmark line")
     args = ap.parse_args()
 
@@ -204,7 +367,6 @@ def main():
         print(msg, file=sys.stderr, flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2008_11326_amd as gpp
@@ -212,91 +374,63 @@ def main():
     from paper_2008_11326_amd import inputs as I
 
     _lib.load()  # fail loudly if the HIP library is missing
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
     if args.leg != "all":
-        stream = torch.cuda.current_stream(torch.device("cuda:0"))
-        leg = adjoint_leg if args.leg == "adjoint" else batched_leg
+        leg = {"adjoint": adjoint_leg, "batched": batched_leg, "si": si_leg}[args.leg]
         log(f"[bench] {args.leg} leg only")
         print(json.dumps({"leg": args.leg, **leg(gpp, I, stream)}), flush=True)
         return
-    wl = I.WORKLOADS[args.workload]
+
+    r, prob, res = fwd_leg(gpp, I, args.workload, args.steps, args.warmup, stream)
+    wl = r["workload"]
     d = wl.dims
-    log(f"[bench] generating {wl.name}")
-    t0 = time.perf_counter()
-    prob = I.make_problem(d, wl.seed, wl.pole_fraction)
-    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
-
-    dev = torch.device("cuda:0")
-    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    t_in = [to(a) for a in prob.arrays()]
-    ach = torch.empty(d.nfreq, dtype=torch.complex128, device=dev)
-    asx = torch.empty(d.nfreq, dtype=torch.complex128, device=dev)
-    ws = torch.empty(gpp.fwd_workspace_bytes(*d.as_tuple()), dtype=torch.uint8,
-                     device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    def step():
-        gpp.sigma_fwd(*t_in, nvband=d.nvband, out=(ach, asx), workspace=ws,
-                      stream=stream.cuda_stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # events on the stream the kernels are launched on
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    t_all0 = torch.cuda.Event(enable_timing=True)
-    t_all1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t_all0.record(stream)
-    for a, b in ev:
-        a.record(stream)
-        step()
-        b.record(stream)
-    t_all1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    total_ms = t_all0.elapsed_time(t_all1)
-    per_launch_ms = [a.elapsed_time(b) for a, b in ev]
-    ms_per_step = total_ms / args.steps
-    launch_ms = sum(per_launch_ms) / len(per_launch_ms)
-    log(f"[bench] {args.steps} steps: {total_ms:.3f} ms on device, {wall * 1e3:.3f} ms wall; "
-        f"per launch min {min(per_launch_ms):.3f} max {max(per_launch_ms):.3f} ms")
-
-    terms = d.ch_terms + d.sx_terms
-    flops = FLOP_PER_TERM * terms
-    value = flops / (ms_per_step * 1e-3) / 1e12
-    achieved = flops / (launch_ms * 1e-3) / 1e12
-
+    q = rates(wl, r["launch_ms"], r["ms_per_step"])
+    counted = "counted_tflops" in q
+    value = q["counted_tflops"] if counted else q["algorithmic_tflops"]
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "number_bands": d.number_bands,
                    "nvband": d.nvband, "ncouls": d.ncouls, "ngpown": d.ngpown,
                    "nfreq": d.nfreq, "seed": wl.seed,
                    "pole_fraction": wl.pole_fraction},
+        "value_kind": ("hardware-counted fp64 FLOPs per launch (" + q["counters"] +
+                       ") / measured time" if counted else
+                       "algorithmic (21 per term): no counter record matches these sources"),
         "pct_fp64_peak": round(100.0 * value / FP64_VECTOR_PEAK_TFLOPS, 2),
-        "terms_per_s": terms / (ms_per_step * 1e-3),
-        "roofline": {"bound": "alu", "achieved": round(achieved, 4),
+        "algorithmic_tflops": round(q["algorithmic_tflops"], 4),
+        "pct_fp64_peak_algorithmic": round(100.0 * q["algorithmic_tflops"] /
+                                           FP64_VECTOR_PEAK_TFLOPS, 2),
+        "terms_per_s": q["terms_per_s"],
+        "roofline": {"bound": "alu", "achieved": round(q["algorithmic_tflops_launch"], 4),
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic(wl.name),
-                     "kernel": "gpp::fwd_tiles<3,2> + two reduce_rows<3> (one gpp_sigma_fwd)",
-                     "launch_ms": round(launch_ms, 4)},
+                     "frac": round(q["algorithmic_tflops_launch"] /
+                                   FP64_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": q.get("traffic"),
+                     "kernel": f"gpp::fwd_tiles<{d.nfreq},2> + two reduce_rows<{d.nfreq}> "
+                               f"(one gpp_sigma_fwd), algorithmic FLOPs",
+                     "launch_ms": round(r["launch_ms"], 4)},
+        "max_rel_err_vs_oracle": max_rel_err(args.workload, res),
     }
-    res = (ach.cpu().numpy(), asx.cpu().numpy())
-    from tests.gpu_helpers import load_golden, rel_errors
-    gold = load_golden(args.workload)
-    if gold is not None:
-        e = max(rel_errors(res[0], gold["ach"], gold["ach_abs_sum"]).max(),
-                rel_errors(res[1], gold["asx"], gold["asx_abs_sum"]).max())
-        out["max_rel_err_vs_oracle"] = float(e)
+    if counted:
+        out["fp64_counted"] = {
+            "flops_per_launch": q["counted_flops_per_launch"],
+            "fma_share": round(q["fma_share"], 4),
+            "fma_ceiling_tflops": round(q["fma_ceiling_tflops"], 3),
+            "pct_of_fma_ceiling": round(100.0 * value / q["fma_ceiling_tflops"], 2),
+            "source": q["counters"]}
+    if q.get("traffic"):
+        out["hbm_gbps"] = round(q["traffic"] / (r["launch_ms"] * 1e-3) / 1e9, 1)
     if not args.no_extras:
-        del t_in, ws
-        torch.cuda.empty_cache()
+        log("[bench] fp64 FMA microbenchmark")
+        peak = fma_peak_leg(stream)
+        out["fma_microbench"] = {"tflops": round(peak, 3),
+                                 "pct_of_measured_fma_peak": round(100.0 * value / peak, 2)}
+        log("[bench] Si-shaped leg")
+        out["si"] = si_leg(gpp, I, stream)
         log("[bench] adjoint leg")
         out["adjoint"] = adjoint_leg(gpp, I, stream)
         log("[bench] batched leg")

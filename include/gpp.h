@@ -32,6 +32,10 @@
  *    overwritten, never accumulated into.
  *  - Arguments are validated before anything is enqueued; a failed check
  *    returns GPP_ERR_INVALID (or GPP_ERR_WORKSPACE) and touches nothing.
+ *    Then the current HIP device must be a gfx950: otherwise (another
+ *    target, or no device at all) the call returns GPP_ERR_UNSUPPORTED and
+ *    enqueues nothing.  The answer is cached per device after the first
+ *    query, so the check costs one hipGetDevice per call.
  *    HIP runtime failures return GPP_ERR_HIP.  gpp_last_error() gives a
  *    thread-local message for the most recent failure.  No C++ exception
  *    crosses this interface.
@@ -158,7 +162,9 @@ typedef struct gpp_plan gpp_plan;
  * taken from the tuning cache, see below).  Candidates: the flat grid (the
  * untuned default) and the persistent schedules 0-3 of gpp_plan_info, each
  * with its tile variants; the environment variable GPP_BATCHED_SCHEDULE=<n>
- * keeps only schedule n (and bypasses the cache).  *out is NULL on failure.
+ * keeps only schedule n, and GPP_BATCHED_BANDS=<b> only the persistent
+ * candidates with b bands per group (either bypasses the cache; for
+ * tests).  *out is NULL on failure.
  */
 gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan **out);
 

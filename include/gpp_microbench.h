@@ -5,7 +5,9 @@
  *
  * Each enqueues one kernel on `stream` (hipStream_t, NULL = default) and
  * returns without synchronising; the caller times it with events.
- * Return 0 on success, 1 on invalid arguments, 2 on a HIP launch error.
+ * Return 0 on success, 1 on invalid arguments, 2 on a HIP launch error,
+ * 5 when the current device is not a gfx950 (or there is none); on 1 and 5
+ * nothing is enqueued.
  */
 #ifndef GPP_MICROBENCH_H
 #define GPP_MICROBENCH_H

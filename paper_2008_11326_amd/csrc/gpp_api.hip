@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "gpp.h"
 #include "gpp_internal.h"
 
@@ -91,9 +93,40 @@ gpp_status check_inputs(const gpp::Dims32 &d, const gpp_inputs *in, gpp::DevInpu
     return GPP_OK;
 }
 
+// Devices whose answer is cached (ids beyond this are queried every call).
+constexpr int kMaxCachedDevices = 64;
+
+gpp_status check_device(const char *who)
+{
+    // per device id: 0 = not yet queried, 1 = gfx950, -1 = another target
+    static std::atomic<signed char> verdict[kMaxCachedDevices];
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GPP_ERR_UNSUPPORTED, "%s: no HIP device (%s)", who, hipGetErrorString(e));
+    }
+    signed char v = (dev >= 0 && dev < kMaxCachedDevices)
+                        ? verdict[dev].load(std::memory_order_relaxed)
+                        : (signed char)0;
+    if (v == 0) {
+        hipDeviceProp_t prop;
+        if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
+            return hip_fail(e, "device query");
+        v = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+        if (dev >= 0 && dev < kMaxCachedDevices) verdict[dev].store(v, std::memory_order_relaxed);
+        if (v < 0)
+            return fail(GPP_ERR_UNSUPPORTED, "%s: device %d is %s, not gfx950", who, dev,
+                        prop.gcnArchName);
+    }
+    if (v < 0) return fail(GPP_ERR_UNSUPPORTED, "%s: device %d is not gfx950", who, dev);
+    return GPP_OK;
+}
+
 }  // namespace gpp
 
 using gpp::check_array;
+using gpp::check_device;
 using gpp::check_dims;
 using gpp::check_inputs;
 using gpp::fail;
@@ -130,6 +163,7 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in, double *ach
                     workspace_bytes, workspace ? "" : " (NULL)");
     if (misaligned(workspace, 16))
         return fail(GPP_ERR_INVALID, "workspace is not 16-byte aligned");
+    if ((s = check_device("gpp_sigma_fwd"))) return s;
     hipError_t e = gpp::launch_fwd(d, din, reinterpret_cast<double2 *>(achtemp),
                                    reinterpret_cast<double2 *>(asxtemp), workspace,
                                    static_cast<hipStream_t>(stream));
@@ -172,6 +206,7 @@ gpp_status gpp_sigma_bwd(const gpp_dims *dims, const gpp_inputs *in,
                     workspace_bytes, workspace ? "" : " (NULL)");
     if (misaligned(workspace, 256))
         return fail(GPP_ERR_INVALID, "workspace is not 256-byte aligned");
+    if ((s = check_device("gpp_sigma_bwd"))) return s;
     gpp::BwdOutputs out{reinterpret_cast<double2 *>(grad_aqsmtemp),
                         reinterpret_cast<double2 *>(grad_aqsntemp),
                         reinterpret_cast<double2 *>(grad_I_eps_array),

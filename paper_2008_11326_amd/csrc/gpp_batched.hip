@@ -355,22 +355,31 @@ batched_reduce(const double *__restrict__ partials, int nwaves, double2 *__restr
     }
 }
 
+// The kernel of a tile variant, or nullptr where its batch inversion would
+// hold more than 12 denominators (columns x bands x frequencies), which the
+// plan never asks for.
 template <int NW, int BU>
 static const void *persistent_ptr(int sched)
 {
-    if (sched == kSchedFlat) return reinterpret_cast<const void *>(&batched_flat<NW, BU>);
-    return (sched == kSchedQueue || sched == kSchedXcdQueues)
-               ? reinterpret_cast<const void *>(&batched_queue<NW, BU>)
-               : reinterpret_cast<const void *>(&batched_persistent<NW, BU>);
+    if (sched == kSchedFlat) {
+        if constexpr (fwd_cols(NW) * BU * NW <= 12)
+            return reinterpret_cast<const void *>(&batched_flat<NW, BU>);
+        return nullptr;
+    }
+    if constexpr (bat_cols(NW) * BU * NW <= 12)
+        return (sched == kSchedQueue || sched == kSchedXcdQueues)
+                   ? reinterpret_cast<const void *>(&batched_queue<NW, BU>)
+                   : reinterpret_cast<const void *>(&batched_persistent<NW, BU>);
+    return nullptr;
 }
 
 const void *batched_kernel(int nw, int bu, int sched)
 {
-#define GPP_K(NWV)                                                     \
-    case NWV:                                                          \
-        if (bu == 1) return persistent_ptr<NWV, 1>(sched);             \
-        if (bu == 2 && NWV <= 4) return persistent_ptr<NWV, 2>(sched); \
-        if (bu == 3 && NWV <= 3) return persistent_ptr<NWV, 3>(sched); \
+#define GPP_K(NWV)                                               \
+    case NWV:                                                    \
+        if (bu == 1) return persistent_ptr<NWV, 1>(sched);       \
+        if (bu == 2) return persistent_ptr<NWV, 2>(sched);       \
+        if (bu == 3) return persistent_ptr<NWV, 3>(sched);       \
         return nullptr;
     switch (nw) {
         GPP_K(1) GPP_K(2) GPP_K(3) GPP_K(4) GPP_K(5) GPP_K(6) GPP_K(7) GPP_K(8)

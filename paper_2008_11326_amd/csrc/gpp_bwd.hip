@@ -37,7 +37,11 @@ namespace gpp {
 constexpr int kBwdWaves = 4;
 constexpr int kBwdThreads = kBwdWaves * kWave;
 constexpr int kRowsPerBlock = kBwdWaves * kWave;  // g rows per pairs workgroup
-constexpr int kBwdGroup = 3;                       // bands per batch-inverted group
+// Bands per batch-inverted group: 3, or 1 with more than four frequencies,
+// so that a group never holds more than 12 denominators (the range for
+// which batch_reciprocal's (Im om)^2 >= 2^-60 lane test keeps every prefix
+// product normal).
+constexpr int bwd_group(int nw) { return nw <= 4 ? 3 : 1; }
 constexpr int kChunk = 48;                         // bands per LDS flush (multiple of kSlab)
 constexpr int kSlab = 6;                           // bands per in-wave transpose (two groups)
 constexpr int kOctet = 8;                          // lanes that share one band's row sum
@@ -66,7 +70,8 @@ constexpr int kBandTile = GPP_BWD_BAND_TILE;       // bands per bands-kernel wav
 constexpr long kBandsWaveSlots = 256L * 4 * GPP_BWD_BANDS_WAVES;
 constexpr int kBandsRounds = GPP_BWD_BANDS_ROUNDS;
 constexpr int kMinSegCols = 64;
-static_assert(kBandTile % kBwdGroup == 0, "band tile must be whole groups");
+static_assert(kBandTile % bwd_group(1) == 0 && kBandTile % bwd_group(8) == 0,
+              "band tile must be whole groups");
 
 // Upstream gradient scaled for the kernels: gh[w] = ga[w]/2 and
 // xgh[w][n] = wx[w][n] ga[w]/2, written once by bwd_prepare.
@@ -293,14 +298,14 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
                 //   T = sum_w xgh_w r_w^2,  U = sum_w xgh_w dr_w r_w^2:
                 // four complex-by-real multiply-adds per term.
 #pragma unroll 1
-                for (int q0 = 0; q0 < kSlab; q0 += kBwdGroup) {
-                    constexpr int Kt = kBwdGroup * NW;
+                for (int q0 = 0; q0 < kSlab; q0 += bwd_group(NW)) {
+                    constexpr int Kt = bwd_group(NW) * NW;
                     double r[Kt], drs[Kt], dcs[Kt];
                     const int ng0 = opaque_uniform(__builtin_amdgcn_readfirstlane(b0 + q0));
-                    group_reciprocals<NW, kBwdGroup, GPP_EXEC_MASK != 2>(
+                    group_reciprocals<NW, bwd_group(NW), GPP_EXEC_MASK != 2>(
                         ng0, nb, wx, ps.a, ps.wi2, ps.thr, ps.wide, r, drs, dcs);
 #pragma unroll
-                    for (int u = 0; u < kBwdGroup; ++u) {
+                    for (int u = 0; u < bwd_group(NW); ++u) {
                         const int nn = ng0 + u;
                         cplx S = cmake(0.0, 0.0), R = S, T = S, U = S;
 #pragma unroll
@@ -373,10 +378,10 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
             while (n < b1) {
                 // bands n .. n+cnt-1 form one batch-inverted group
                 const bool occ = n < nv;
-                const int cnt = (!occ && n + kBwdGroup <= b1) ? kBwdGroup : 1;
-                cplx K[kBwdGroup], L[kBwdGroup];
-                if (cnt == kBwdGroup) {
-                    ch_bands_kl<NW, kBwdGroup, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2,
+                const int cnt = (!occ && n + bwd_group(NW) <= b1) ? bwd_group(NW) : 1;
+                cplx K[bwd_group(NW)], L[bwd_group(NW)];
+                if (cnt == bwd_group(NW)) {
+                    ch_bands_kl<NW, bwd_group(NW), true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2,
                                                      ps.thr, ps.wide, K, L);
                 } else {
                     cplx K1[1], L1[1];
@@ -386,7 +391,7 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
                     L[0] = L1[0];
                 }
 #pragma unroll
-                for (int u = 0; u < kBwdGroup; ++u) {
+                for (int u = 0; u < bwd_group(NW); ++u) {
                     if (u >= cnt) break;  // wave-uniform
                     const int nn = n + u;
                     cplx Z = cmul(cw, K[u]);
@@ -476,7 +481,7 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
                                            gptr<double2> gh, gptr<double2> xgh,
                                            cplx (&acc)[kBandTile])
 {
-    constexpr int Kt = kBwdGroup * NW;
+    constexpr int Kt = bwd_group(NW) * NW;
     // om and e of the next column are loaded one iteration ahead, so their
     // latency overlaps this column's arithmetic
     cplx om_next = cload(wt + (size_t)p_lo * ng + gc), e_next = cload(ieps + (size_t)p_lo * ng + gc);
@@ -495,12 +500,12 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
         const cplx c1 = cmul(vce, cmake(a, -b));
         const cplx c2 = cscale(wtr, vce);
 #pragma unroll
-        for (int u0 = 0; u0 < kBandTile; u0 += kBwdGroup) {
+        for (int u0 = 0; u0 < kBandTile; u0 += bwd_group(NW)) {
             const int n = nfirst + u0;
             double xs[Kt], dc[Kt], r[Kt];
             bool isA[Kt];
 #pragma unroll
-            for (int u = 0; u < kBwdGroup; ++u)
+            for (int u = 0; u < bwd_group(NW); ++u)
 #pragma unroll
                 for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
 #pragma unroll
@@ -512,7 +517,7 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
             }
             batch_reciprocal<Kt>(dc, r, wide);
 #pragma unroll
-            for (int u = 0; u < kBwdGroup; ++u) {
+            for (int u = 0; u < bwd_group(NW); ++u) {
 #if GPP_EXEC_MASK == 2
                 // the first frequency starts S and R through a select, the
                 // others add under an execution mask written by the compare
@@ -582,17 +587,17 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int p_lo, 
         const cplx vce = cmake(ps.ve.re, -ps.ve.im);           // vcoul conj(e)
         const cplx vcw = cmul(vce, cmake(ps.om.re, -ps.om.im));  // vcoul conj(e om)
 #pragma unroll
-        for (int u0 = 0; u0 < kBandTile; u0 += kBwdGroup) {
+        for (int u0 = 0; u0 < kBandTile; u0 += bwd_group(NW)) {
             const int n = n0 + u0;
             if (n >= nb) break;  // wave-uniform
-            cplx K[kBwdGroup], L[kBwdGroup];
-            const bool full = n + kBwdGroup <= nb && n >= nv;
+            cplx K[bwd_group(NW)], L[bwd_group(NW)];
+            const bool full = n + bwd_group(NW) <= nb && n >= nv;
             if (full) {
-                ch_bands_kl<NW, kBwdGroup, false>(n, nb, wx, gh, nullptr, ps.a, ps.b, ps.wi2,
+                ch_bands_kl<NW, bwd_group(NW), false>(n, nb, wx, gh, nullptr, ps.a, ps.b, ps.wi2,
                                                   ps.thr, ps.wide, K, L);
             } else {
 #pragma unroll
-                for (int u = 0; u < kBwdGroup; ++u) {
+                for (int u = 0; u < bwd_group(NW); ++u) {
                     K[u] = cmake(0.0, 0.0);
                     if (n + u < nb) {
                         cplx K1[1], L1[1];
@@ -603,7 +608,7 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int p_lo, 
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kBwdGroup; ++u) {
+            for (int u = 0; u < bwd_group(NW); ++u) {
                 const int nn = n + u;
                 if (nn < nb) {
                     // vcoul conj(e) Z = vcoul conj(e om) K [+ vcoul conj(e) KS]

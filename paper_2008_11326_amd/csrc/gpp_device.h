@@ -132,6 +132,7 @@ __device__ __forceinline__ double rcp_batch(double d) {
 template <int K>
 __device__ __forceinline__ void batch_reciprocal(const double (&d)[K], double (&r)[K],
                                                  bool batch_ok = true) {
+    static_assert(K <= 12, "the 2^-60 lane bound keeps products of at most 12 factors normal");
     double c[K];
     c[0] = d[0];
 #pragma unroll

@@ -118,6 +118,10 @@ gpp_status check_dims(const gpp_dims *d, Dims32 *out);
 gpp_status check_array(const char *name, const void *p, int64_t elems, size_t align);
 gpp_status check_inputs(const Dims32 &d, const gpp_inputs *in, DevInputs *out);
 bool misaligned(const void *p, size_t a);
+// GPP_OK when the current HIP device is a gfx950, else GPP_ERR_UNSUPPORTED
+// (no device, or another target) with a message naming `who`.  The device's
+// answer is cached after the first query.
+gpp_status check_device(const char *who);
 
 FwdGeometry fwd_geometry(const Dims32 &d);
 BwdGeometry bwd_geometry(const Dims32 &d);

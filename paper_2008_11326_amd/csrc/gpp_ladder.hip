@@ -562,6 +562,7 @@ gpp_status gpp_ladder_fwd(int32_t step, const gpp_dims *dims, const gpp_inputs *
                          workspace_bytes, workspace ? "" : " (NULL)");
     if (gpp::misaligned(workspace, 16))
         return gpp::fail(GPP_ERR_INVALID, "workspace is not 16-byte aligned");
+    if ((s = gpp::check_device("gpp_ladder_fwd"))) return s;
     hipError_t e = gpp::launch_ladder(step, d, din, reinterpret_cast<double2 *>(achtemp),
                                       reinterpret_cast<double2 *>(asxtemp),
                                       static_cast<char *>(workspace),

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gpp_internal.h"
 #include "gpp_microbench.h"
 
 namespace {
@@ -78,6 +79,7 @@ extern "C" {
 int gpp_mb_fp64_fma(double *out, int blocks, int iters, void *stream, double *flops)
 {
     if (!out || blocks <= 0 || iters <= 0) return 1;
+    if (gpp::check_device("gpp_mb_fp64_fma") != GPP_OK) return 5;
     hipLaunchKernelGGL(mb_fma, dim3(blocks), dim3(256), 0, (hipStream_t)stream, out, 1.5,
                        iters);
     if (flops) *flops = 2.0 * kChains * (double)iters * 256.0 * blocks;
@@ -88,6 +90,7 @@ int gpp_mb_copy(const void *src, void *dst, int64_t bytes, int blocks, void *str
 {
     if (!src || !dst || bytes <= 0 || bytes % 16 || blocks <= 0) return 1;
     if (((uintptr_t)src | (uintptr_t)dst) % 16) return 1;
+    if (gpp::check_device("gpp_mb_copy") != GPP_OK) return 5;
     hipLaunchKernelGGL(mb_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                        (const double2 *)src, (double2 *)dst, (long)(bytes / 16));
     return hipGetLastError() == hipSuccess ? 0 : 2;
@@ -99,6 +102,7 @@ int gpp_mb_read(const void *buf, int64_t window_bytes, int shared, int blocks, i
     if (!buf || !out || window_bytes <= 0 || window_bytes % 16 || blocks <= 0 || reps <= 0)
         return 1;
     if ((uintptr_t)buf % 16) return 1;
+    if (gpp::check_device("gpp_mb_read") != GPP_OK) return 5;
     hipLaunchKernelGGL(mb_read, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                        (const double2 *)buf, (long)(window_bytes / 16), shared ? 1 : 0, reps,
                        out);

@@ -207,7 +207,7 @@ struct gpp_plan {
     std::string key;
     size_t ws_bytes = 0;
     int max_waves = 0;
-    bool forced = false;  // candidates restricted by GPP_BATCHED_SCHEDULE
+    bool forced = false;  // candidates restricted by GPP_BATCHED_SCHEDULE/_BANDS
     // descriptor table (nstates + 1 entries, then kXcdCount + 1 chunk
     // boundaries): device copy, pinned staging, event guarding reuse
     gpp::StateDesc *d_desc = nullptr, *h_desc = nullptr;
@@ -539,14 +539,14 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
 
     hipError_t e;
     hipDeviceProp_t prop;
+    if (gpp_status ds = gpp::check_device("gpp_plan_create")) {
+        delete pl;
+        return ds;
+    }
     if ((e = hipGetDevice(&pl->device)) != hipSuccess ||
         (e = hipGetDeviceProperties(&prop, pl->device)) != hipSuccess) {
         delete pl;
         return hip_fail(e, "gpp_plan_create: device query");
-    }
-    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
-        delete pl;
-        return fail(GPP_ERR_UNSUPPORTED, "device %s is not gfx950", prop.gcnArchName);
     }
     // candidates: bands per group (register budget allows fewer for many
     // frequencies) x schedule order; the first is the untuned default
@@ -565,6 +565,16 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
     int only = -1;
     if (const char *f = getenv("GPP_BATCHED_SCHEDULE")) {
         only = atoi(f);
+        pl->forced = true;
+    }
+    // GPP_BATCHED_BANDS=<b> keeps only the persistent candidates with b bands
+    // per group (tests; the flat grid always runs the plain forward's tile)
+    if (const char *f = getenv("GPP_BATCHED_BANDS")) {
+        const int only_bu = atoi(f);
+        std::vector<int> keep;
+        for (int bu : bus)
+            if (bu == only_bu) keep.push_back(bu);
+        bus = keep;
         pl->forced = true;
     }
     size_t rows = 0;

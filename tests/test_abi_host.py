@@ -236,3 +236,37 @@ def test_ladder_names_and_validation(lib):
     big = _dims(nb=512, ng=32768, npw=1638)
     assert lib.gpp_ladder_workspace(7, C.byref(big)) >= \
         lib.gpp_ladder_workspace(6, C.byref(big)) + 512 * 1638 * 16
+
+
+def _hip_device_count():
+    """Devices the HIP runtime sees (hipGetDeviceCount), or None if the
+    runtime cannot be asked."""
+    try:
+        hip = C.CDLL("libamdhip64.so")
+    except OSError:
+        return None
+    n = C.c_int(-1)
+    rc = hip.hipGetDeviceCount(C.byref(n))
+    return n.value if rc == 0 else 0
+
+
+@pytest.mark.skipif(_hip_device_count() != 0,
+                    reason="checks the no-device path; this host has (or may have) a GPU")
+def test_no_device_is_unsupported(lib):
+    """With valid arguments and no device, every compute entry point returns
+    GPP_ERR_UNSUPPORTED and enqueues nothing (the addresses are fake)."""
+    d = _dims()
+    assert _call(lib, d, _inputs()) == 5
+    assert "no HIP device" in lib.gpp_last_error().decode()
+    assert _bwd(lib, d, _inputs(), outs=(FAKE + 0xB00000, 0, 0, 0)) == 5
+    assert "gpp_sigma_bwd" in lib.gpp_last_error().decode()
+    for step in (0, 10):
+        assert _ladder_call(lib, step, d) == 5
+    handle = C.c_void_p()
+    ok = (_lib.GppDims * 1)(_lib.GppDims(8, 2, 100, 10, 3))
+    assert lib.gpp_plan_create(1, ok, C.byref(handle)) == 5 and handle.value is None
+    flops = C.c_double(0.0)
+    assert lib.gpp_mb_fp64_fma(C.c_void_p(FAKE), 1, 1, None, C.byref(flops)) == 5
+    assert lib.gpp_mb_copy(C.c_void_p(FAKE), C.c_void_p(FAKE + 0x100000), 4096, 1, None) == 5
+    assert lib.gpp_mb_read(C.c_void_p(FAKE), 4096, 0, 1, 1, C.c_void_p(FAKE + 0x100000),
+                           None) == 5

@@ -78,6 +78,61 @@ def test_every_schedule_vs_oracle(gpp, uneven, sched, monkeypatch):
     plan.close()
 
 
+def _plan_bands(nw):
+    """Bands per group the plan offers its persistent kernels for nw
+    frequencies (gpp_plan_create)."""
+    return (3, 2) if nw <= 3 else ((2, 1) if nw == 4 else (1,))
+
+
+# every batched tile variant: frequency count x persistent schedule x bands
+# per group, and the flat grid (the plain forward's tile) per frequency count
+VARIANTS = [(nw, sched, bu) for nw in (1, 2, 3, 4, 5, 8) for sched in (0, 1, 2, 3)
+            for bu in _plan_bands(nw)] + [(nw, 4, None) for nw in (1, 2, 4, 5, 8)]
+
+
+@pytest.fixture(scope="module")
+def uneven_by_nfreq():
+    """The uneven states with another frequency count (one set kept at a
+    time), their oracle outputs and device copies."""
+    held = {}
+
+    def get(nw):
+        if nw not in held:
+            held.clear()
+            dims = [I.Dims(d.number_bands, d.nvband, d.ncouls, d.ngpown, nw) for d in UNEVEN]
+            probs = [I.make_problem(d, [19, k], 0.05 if k % 2 else 0.0)
+                     for k, d in enumerate(dims)]
+            held[nw] = (probs, [oracle.sigma_fwd(p) for p in probs],
+                        [to_device(p) for p in probs])
+        return held[nw]
+    return get
+
+
+@pytest.mark.parametrize("nw,sched,bu", VARIANTS,
+                         ids=[f"nw{a}-s{b}-bu{c}" for a, b, c in VARIANTS])
+def test_every_tile_variant_vs_oracle(gpp, uneven_by_nfreq, nw, sched, bu, monkeypatch):
+    """One schedule and one tile variant at a time (GPP_BATCHED_SCHEDULE,
+    GPP_BATCHED_BANDS) for 1 to 8 frequencies, on the uneven states, against
+    the oracle."""
+    import torch
+    monkeypatch.setenv("GPP_BATCHED_SCHEDULE", str(sched))
+    if bu is not None:
+        monkeypatch.setenv("GPP_BATCHED_BANDS", str(bu))
+    probs, refs, dev = uneven_by_nfreq(nw)
+    say(f"[batched] nfreq {nw} schedule {sched} bands {bu}")
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    ach, asx = gpp.sigma_batched(plan, dev)
+    torch.cuda.synchronize()
+    info = plan.info()
+    assert info["schedule"] == sched and info["from_cache"] == 0
+    if bu is not None:
+        assert info["bands_per_group"] == bu
+    for k, ref in enumerate(refs):
+        assert_parity(ach[k].cpu().numpy(), ref[0], ref[2], f"state {k} achtemp")
+        assert_parity(asx[k].cpu().numpy(), ref[1], ref[3], f"state {k} asxtemp")
+    plan.close()
+
+
 def test_tiny_imaginary_lanes(gpp, tmp_path, monkeypatch):
     """States whose tiles mix lanes with (Im om)^2 below 2^-60 (one-by-one
     reciprocals, exact poles) with ordinary lanes, against the oracle."""
@@ -207,7 +262,11 @@ def test_batched_workload_all_states_against_golden(gpp, tmp_path, monkeypatch):
         pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} free")
     monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
     say(f"[batched] uploading all {len(dims)} states ({need / 2**30:.1f} GiB)")
-    dev = [to_device(prob) for _, prob in I.make_batched()]
+    dev = []
+    for s, prob in I.make_batched():
+        dev.append(to_device(prob))
+        if s % 8 == 7:
+            say(f"[batched] {s + 1} states uploaded")
     plan = gpp.Plan([d.as_tuple() for d in dims])
     ach, asx = gpp.sigma_batched(plan, dev)
     torch.cuda.synchronize()

@@ -155,6 +155,53 @@ def test_adjoint_workload_against_oracle(gpp, adjoint_case):
     assert np.all(g["aqsmtemp"][:, npw:] == 0)
 
 
+def _slice_fd(prob, ga, gs, name, i, j, z0, step):
+    """Central difference of the oracle's slice-restricted loss at entry
+    (i, j) with step `step` along Re and Im, and whether any touched term
+    changes branch at the four stencil points."""
+    _, b0 = oracle.slice_loss(prob, ga, gs, name, i, j, z0)
+    fd, same = [], True
+    for s in (step, 1j * step):
+        lp, bp = oracle.slice_loss(prob, ga, gs, name, i, j, z0 + s)
+        lm, bm = oracle.slice_loss(prob, ga, gs, name, i, j, z0 - s)
+        same &= np.array_equal(bp, b0) and np.array_equal(bm, b0)
+        fd.append((lp - lm) / (2 * step))
+    return complex(fd[0], fd[1]), same
+
+
+def test_adjoint_workload_slice_fd_all_entries(gpp, adjoint_case):
+    """All 1000 drawn entries per array: the GPU gradient against central
+    differences (h = 1e-6) of the oracle's loss restricted to the terms that
+    touch the entry (so the quotient does not cancel against the whole sum).
+    Stencils that move a touched term across a branch boundary are skipped.
+    The bar is 1e-7 of the entry's scale plus the stencil's own truncation
+    error, estimated from a second step 2h (the two quotients differ by
+    three times the h^2 term): a few entries sit next to a pole of the
+    exchange term (x + om ~ 0), where the h^2 term reaches 1e-7."""
+    prob, ga, gs, entries = adjoint_case
+    say("[bwd] adjoint workload: slice finite differences on 4 x 1000 entries")
+    g = gpu_grads(gpp, prob, ga, gs)
+    h = 1e-6
+    for name in ARRAYS:
+        arr = getattr(prob, name)
+        vals = np.array([g[name][i, j] for i, j in entries[name]])
+        floor = 1e-3 * np.median(np.abs(vals))
+        checked = 0
+        worst = 0.0
+        for (i, j), got in zip(entries[name], vals):
+            z0 = arr[i, j]
+            d1, ok1 = _slice_fd(prob, ga, gs, name, i, j, z0, h)
+            d2, ok2 = _slice_fd(prob, ga, gs, name, i, j, z0, 2 * h)
+            if not (ok1 and ok2):
+                continue
+            checked += 1
+            tol = 1e-7 * max(abs(got), floor) + (2.0 / 3.0) * abs(d2 - d1)
+            worst = max(worst, abs(d1 - got) / tol)
+            assert abs(d1 - got) <= tol, (name, i, j, got, d1, d2)
+        say(f"[bwd] {name}: {checked} of {len(vals)} stencils usable, worst error/bar {worst:.3f}")
+        assert checked >= 950, (name, checked)
+
+
 def test_adjoint_workload_finite_differences(gpp, adjoint_case):
     """Central differences (h = 1e-6) of the GPU forward on 50 entries per
     array; stencils that move a touched term across a branch boundary are

@@ -11,6 +11,7 @@
 Loop nest and reductions: paper Sec. II-A; branch: Sec. III v2/v3.
 """
 import json
+import math
 import os
 from fractions import Fraction
 
@@ -46,12 +47,23 @@ with open(os.path.join(GOLDEN, "single_terms.json")) as f:
     SINGLE = json.load(f)["cases"]
 
 
+def _modulus(pair_re, pair_im):
+    """|re + i im| of a complex value given as exact [num, den] pairs."""
+    re, im = Fraction(*pair_re), Fraction(*pair_im)
+    return math.sqrt(re * re + im * im)
+
+
 @pytest.mark.parametrize("case", SINGLE, ids=[c["name"] for c in SINGLE])
 def test_single_term_hand_values(case):
     prob = _single(case)
-    ach, asx, _, _ = oracle.sigma_fwd(prob, nthreads=1)
+    ach, asx, ach_abs, asx_abs = oracle.sigma_fwd(prob, nthreads=1)
     _close(ach[0], _frac(case["achtemp"][0]), _frac(case["achtemp"][1]))
     _close(asx[0], _frac(case["asxtemp"][0]), _frac(case["asxtemp"][1]))
+    # one term each: the sums of |term| are the moduli of the hand values
+    want_ach = _modulus(*case["achtemp"])
+    want_asx = _modulus(*case["asxtemp"])
+    assert abs(ach_abs[0] - want_ach) <= 4e-16 * want_ach
+    assert abs(asx_abs[0] - want_asx) <= 4e-16 * want_asx
     om = complex(*case["wtilde"])
     assert oracle.branch(case["x"], om) == case["branch"]
     # an unoccupied band contributes nothing to asxtemp
@@ -145,8 +157,24 @@ def test_single_pole_closed_form():
     nb, nv, ng, npw = len(xs), 2, 300, 40
     prob = _uniform_problem(nb, nv, ng, npw, xs, om.c(), e.c(), a.c(), b.c(),
                             float(v))
-    ach, asx, _, _ = oracle.sigma_fwd(prob, nthreads=3)
+    ach, asx, ach_abs, asx_abs = oracle.sigma_fwd(prob, nthreads=3)
     pref = _Q(npw * ng) * a * b.conj() * e
+    unit = a * b.conj() * e
+    want_abs = [[0.0] * 3, [0.0] * 3]
+    for w in range(3):
+        for n in range(nb):
+            x = _Q(Fraction(xs[n][w]))
+            d = x + _Q(-om.re, -om.im)
+            s = x + om
+            if d.re ** 2 + d.im ** 2 > Fraction(1, 4):
+                tch = unit * _Q(v / 2) * om * d.inv()
+                tsx = unit * _Q(v) * om * om * (d * s).inv()
+            else:
+                tch = _Q(0)
+                tsx = unit * _Q(v) * _Q(Fraction(-1, 2)) * om * s.inv()
+            want_abs[0][w] += npw * ng * _abs_q(tch)
+            if n < nv:
+                want_abs[1][w] += npw * ng * _abs_q(tsx)
     for w in range(3):
         s_ch, s_sx = _Q(0), _Q(0)
         for n in range(nb):
@@ -165,6 +193,41 @@ def test_single_pole_closed_form():
         want_sx = (pref * _Q(v) * s_sx).c()
         assert abs(ach[w] - want_ch) <= 1e-14 * abs(want_ch)
         assert abs(asx[w] - want_sx) <= 1e-14 * abs(want_sx)
+        # every (p, g) repeats the same term, so the sums of |term| are
+        # NP NG sum_n |term_n|, each modulus from its exact square
+        assert abs(ach_abs[w] - want_abs[0][w]) <= 1e-14 * want_abs[0][w]
+        assert abs(asx_abs[w] - want_abs[1][w]) <= 1e-14 * want_abs[1][w]
+
+
+def _abs_q(z):
+    return math.sqrt(z.re * z.re + z.im * z.im)
+
+
+def test_abs_sums_of_cancelling_bands():
+    """Two bands with opposite aqsntemp rows and equal frequencies cancel
+    term by term: the outputs vanish while the sums of |term| are
+    2 NP NG sum_w-wise |term|, which a dropped 1/2, a squared modulus or a
+    signed sum would change."""
+    om = _Q(Fraction(3, 2), Fraction(1, 8))
+    e, a, b, v = _Q(Fraction(3, 4), Fraction(1, 2)), _Q(Fraction(5, 4), Fraction(-1, 2)), \
+        _Q(Fraction(1, 2), Fraction(1, 4)), Fraction(5, 8)
+    xs = [[-1.0, 3.5], [-1.0, 3.5]]          # both bands: A at both frequencies
+    nb, nv, ng, npw = 2, 2, 7, 3
+    prob = _uniform_problem(nb, nv, ng, npw, xs, om.c(), e.c(), a.c(), b.c(),
+                            float(v))
+    prob.aqsntemp[1] = -prob.aqsntemp[0]
+    ach, asx, ach_abs, asx_abs = oracle.sigma_fwd(prob, nthreads=1)
+    unit = a * b.conj() * e
+    for w in range(2):
+        x = _Q(Fraction(xs[0][w]))
+        d = x + _Q(-om.re, -om.im)
+        s = x + om
+        t_ch = _abs_q(unit * _Q(v / 2) * om * d.inv())
+        t_sx = _abs_q(unit * _Q(v) * om * om * (d * s).inv())
+        assert abs(ach_abs[w] - 2 * npw * ng * t_ch) <= 1e-15 * 2 * npw * ng * t_ch
+        assert abs(asx_abs[w] - 2 * npw * ng * t_sx) <= 1e-15 * 2 * npw * ng * t_sx
+        assert abs(ach[w]) <= 1e-15 * ach_abs[w]
+        assert abs(asx[w]) <= 1e-15 * asx_abs[w]
 
 
 def test_pole_cancellation_identity():

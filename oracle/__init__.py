@@ -2,8 +2,9 @@
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It wraps the plain C code in ``gpp_oracle.c`` (fp64,
-compensated sums) and ``gpp_oracle_ld.c`` (long-double brute force), which
-share nothing with the HIP library.  Inputs are numpy arrays in the layouts
+compensated sums) and ``gpp_oracle_ld.c`` (long-double brute force), and
+adds the quasiparticle step on top of the forward's outputs in ``qp.py``;
+none of it shares anything with the HIP library.  Inputs are numpy arrays in the layouts
 documented in ``paper_2008_11326_amd.inputs`` (the shared input generator).
 """
 from __future__ import annotations
@@ -14,9 +15,10 @@ import os
 import numpy as np
 
 from . import build as _build
+from .qp import quasiparticle
 
 __all__ = ["sigma_fwd", "sigma_fwd_slice", "sigma_ld", "branch",
-           "grad_entries", "slice_loss", "KIND", "load"]
+           "grad_entries", "slice_loss", "quasiparticle", "KIND", "load"]
 
 KIND = {"wtilde_array": 0, "I_eps_array": 1, "aqsntemp": 2, "aqsmtemp": 3}
 

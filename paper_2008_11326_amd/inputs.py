@@ -83,6 +83,10 @@ class Problem:
     vcoul: np.ndarray
     wx_array: np.ndarray
     seed: object = None
+    # energy of the quasiparticle state (e_lk) and the spacing of the nfreq
+    # frequencies around it: wx_array[w][n] = e_lk + (w - (nfreq-1)/2) * freq_step - e_n
+    e_lk: Optional[float] = None
+    freq_step: float = 0.5
 
     def arrays(self):
         return (self.aqsmtemp, self.aqsntemp, self.I_eps_array,
@@ -150,7 +154,7 @@ def make_problem(dims: Dims, seed, pole_fraction: float = 0.0) -> Problem:
         d_im = rng.uniform(-1e-6, 1e-6, k)
         wtf = wt.reshape(-1)
         wtf[flat_pg] = wx.reshape(-1)[flat_wn] + d_re + 1j * d_im
-    return Problem(dims, aqsm, aqsn, ieps, wt, vcoul, wx, seed)
+    return Problem(dims, aqsm, aqsn, ieps, wt, vcoul, wx, seed, e_lk=float(e_lk))
 
 
 def make_upstream_grad(nfreq: int, rng) -> tuple:

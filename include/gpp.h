@@ -111,6 +111,31 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
                          double *achtemp, double *asxtemp, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/*
+ * gpp_sigma_qp -- gpp_sigma_fwd followed by the quasiparticle step that
+ * consumes its outputs in the Sigma module the kernel comes from (Sec.
+ * II-A; the paper does not print this step, so the reading below is the
+ * library's).  The nfreq frequencies are equally spaced around the state's
+ * energy: E_w = energy + (w - m) freq_step, m = (nfreq - 1)/2, i.e.
+ * wx_array[w][n] = E_w - e_n.  With Sigma(E_w) = achtemp[w] - asxtemp[w]
+ * (asxtemp is the unsigned screened-exchange sum):
+ *   qp[0], qp[1]  Sigma(E) = Sigma(E_m), re and im
+ *   qp[2], qp[3]  dSigma/dE = (Sigma(E_{m+1}) - Sigma(E_{m-1})) / (2 freq_step)
+ *   qp[4]         Z = 1 / (1 - Re dSigma/dE)
+ *   qp[5]         E_qp = energy + Z (Re Sigma(E) - vxc), the linearised
+ *                 quasiparticle energy for the exchange-correlation value vxc
+ *   dims, in:       as gpp_sigma_fwd; nfreq must be odd and at least 3
+ *   freq_step:      host, finite and > 0; energy, vxc: host, finite
+ *   achtemp, asxtemp: device, complex [nfreq], overwritten (as gpp_sigma_fwd)
+ *   qp:             device, double [6], 8-byte aligned, overwritten
+ *   workspace:      device, >= gpp_sigma_fwd_workspace(dims) bytes, 16-byte aligned
+ * The step runs inside the forward's last reduction kernel (no extra
+ * launch).  An empty sum gives Sigma = 0, Z = 1, E_qp = energy - vxc.
+ */
+gpp_status gpp_sigma_qp(const gpp_dims *dims, const gpp_inputs *in, double freq_step,
+                        double energy, double vxc, double *achtemp, double *asxtemp, double *qp,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
 /* Bytes of device workspace gpp_sigma_bwd needs for `dims` (host-only
  * computation).  It grows as ceil(ncouls/256) * number_bands * ngpown * 16
  * bytes (partial sums of the aqsmtemp gradient), plus, for problems small

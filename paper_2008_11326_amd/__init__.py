@@ -6,6 +6,7 @@ memory and the current stream) into that ABI.
 
     ach, asx = sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
                          vcoul, wx_array, nvband)
+    ach, asx, qp = sigma_qp(..., nvband, freq_step, energy, vxc)  # + Sigma(E), dSigma/dE, Z, E_qp
     grads = sigma_bwd(..., grad_achtemp, grad_asxtemp)   # adjoint
     ach, asx = sigma(...)            # differentiable (GppSigma autograd.Function)
     plan = Plan([dims_0, dims_1, ...])          # many states, one launch
@@ -23,7 +24,7 @@ import ctypes as C
 from . import _lib
 from ._lib import GppError, MAX_NFREQ
 
-__all__ = ["sigma_fwd", "sigma_bwd", "sigma", "GppSigma", "Plan", "sigma_batched",
+__all__ = ["sigma_fwd", "sigma_qp", "sigma_bwd", "sigma", "GppSigma", "Plan", "sigma_batched",
            "fwd_workspace_bytes", "bwd_workspace_bytes", "GppError", "MAX_NFREQ",
            "library_path"]
 
@@ -119,6 +120,40 @@ def sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
                                C.c_void_p(stream))
     _lib.check(st, "gpp_sigma_fwd")
     return ach, asx
+
+
+def sigma_qp(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
+             nvband: int, freq_step: float, energy: float = 0.0, vxc: float = 0.0, *,
+             out=None, workspace=None, stream=None):
+    """achtemp, asxtemp and the quasiparticle quantities via gpp_sigma_qp:
+    returns (achtemp, asxtemp, qp) with qp a float64 [6] tensor holding
+    Sigma(E) re/im, dSigma/dE re/im, Z and E_qp (include/gpp.h).  The nfreq
+    (odd) frequencies are energy + (w - (nfreq-1)/2) freq_step."""
+    torch = _torch()
+    lib = _lib.load()
+    dims, ins, dev = _prepare(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
+                              vcoul, wx_array, nvband)
+    nw = dims.nfreq
+    if out is None:
+        ach = torch.empty(nw, dtype=torch.complex128, device=dev)
+        asx = torch.empty(nw, dtype=torch.complex128, device=dev)
+        qp = torch.empty(6, dtype=torch.float64, device=dev)
+    else:
+        ach, asx, qp = out
+        _check_tensor("achtemp", ach, torch.complex128, (nw,), dev)
+        _check_tensor("asxtemp", asx, torch.complex128, (nw,), dev)
+        _check_tensor("qp", qp, torch.float64, (6,), dev)
+    need = int(lib.gpp_sigma_fwd_workspace(C.byref(dims)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    with torch.cuda.device(dev):
+        st = lib.gpp_sigma_qp(C.byref(dims), C.byref(ins), float(freq_step), float(energy),
+                              float(vxc), _ptr(ach), _ptr(asx), _ptr(qp), _ptr(workspace),
+                              workspace.numel(), C.c_void_p(stream))
+    _lib.check(st, "gpp_sigma_qp")
+    return ach, asx, qp
 
 
 def bwd_workspace_bytes(number_bands, nvband, ncouls, ngpown, nfreq) -> int:

@@ -55,6 +55,9 @@ _SIGNATURES = [
     ("gpp_sigma_fwd", C.c_int,
      [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p,
       C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("gpp_sigma_qp", C.c_int,
+     [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_double, C.c_double, C.c_double,
+      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     ("gpp_sigma_bwd_workspace", C.c_size_t, [C.POINTER(GppDims)]),
     ("gpp_sigma_bwd", C.c_int,
      [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p,

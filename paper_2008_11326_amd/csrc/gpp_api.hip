@@ -171,6 +171,46 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in, double *ach
     return GPP_OK;
 }
 
+gpp_status gpp_sigma_qp(const gpp_dims *dims, const gpp_inputs *in, double freq_step,
+                        double energy, double vxc, double *achtemp, double *asxtemp, double *qp,
+                        void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_last_error[0] = '\0';
+    gpp::Dims32 d;
+    gpp::DevInputs din;
+    gpp_status s;
+    if ((s = check_dims(dims, &d))) return s;
+    if (d.nw < 3 || d.nw % 2 == 0)
+        return fail(GPP_ERR_INVALID, "nfreq=%d: the quasiparticle step needs an odd number of "
+                    "frequencies, at least 3", d.nw);
+    if (!(freq_step > 0.0) || !(freq_step <= 1.0e300))
+        return fail(GPP_ERR_INVALID, "freq_step must be finite and positive");
+    if (!(energy == energy) || !(vxc == vxc) || !(energy - energy == 0.0) ||
+        !(vxc - vxc == 0.0))
+        return fail(GPP_ERR_INVALID, "energy and vxc must be finite");
+    if ((s = check_inputs(d, in, &din))) return s;
+    if ((s = check_array("achtemp", achtemp, d.nw, 16)) ||
+        (s = check_array("asxtemp", asxtemp, d.nw, 16)) || (s = check_array("qp", qp, 6, 8)))
+        return s;
+    const size_t need = gpp_sigma_fwd_workspace(dims);
+    if (!workspace || workspace_bytes < need)
+        return fail(GPP_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu%s", need,
+                    workspace_bytes, workspace ? "" : " (NULL)");
+    if (misaligned(workspace, 16))
+        return fail(GPP_ERR_INVALID, "workspace is not 16-byte aligned");
+    if ((s = check_device("gpp_sigma_qp"))) return s;
+    gpp::QpArgs qa;
+    qa.out = qp;
+    qa.step = freq_step;
+    qa.energy = energy;
+    qa.vxc = vxc;
+    hipError_t e = gpp::launch_fwd(d, din, reinterpret_cast<double2 *>(achtemp),
+                                   reinterpret_cast<double2 *>(asxtemp), workspace,
+                                   static_cast<hipStream_t>(stream), qa);
+    if (e != hipSuccess) return hip_fail(e, "gpp_sigma_qp launch");
+    return GPP_OK;
+}
+
 size_t gpp_sigma_bwd_workspace(const gpp_dims *dims)
 {
     gpp::Dims32 d;

@@ -111,17 +111,48 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
     }
 }
 
+// Quasiparticle quantities from the final sums fin[4 w + 0..3] = achtemp[w]
+// re, im, asxtemp[w] re, im, for nfreq odd and at least 3 (the caller
+// checks): Sigma(E_w) = achtemp[w] - asxtemp[w] (asxtemp is the unsigned
+// exchange sum), dSigma/dE at the middle frequency m by the central
+// difference of its neighbours, Z = 1/(1 - Re dSigma/dE) and the linearised
+// quasiparticle energy E + Z (Re Sigma(E) - V_xc).  out = Sigma re, im,
+// dSigma/dE re, im, Z, E_qp.
+template <int NW>
+__device__ inline void qp_epilogue(const double *fin, const QpArgs &qp)
+{
+    if constexpr (NW >= 3 && NW % 2 == 1) {
+        constexpr int m = (NW - 1) / 2;
+        const double sr = fin[4 * m] - fin[4 * m + 2], si = fin[4 * m + 1] - fin[4 * m + 3];
+        const double hi_r = fin[4 * (m + 1)] - fin[4 * (m + 1) + 2];
+        const double hi_i = fin[4 * (m + 1) + 1] - fin[4 * (m + 1) + 3];
+        const double lo_r = fin[4 * (m - 1)] - fin[4 * (m - 1) + 2];
+        const double lo_i = fin[4 * (m - 1) + 1] - fin[4 * (m - 1) + 3];
+        const double span = 2.0 * qp.step;
+        const double dr = (hi_r - lo_r) / span, di = (hi_i - lo_i) / span;
+        const double z = 1.0 / (1.0 - dr);
+        qp.out[0] = sr;
+        qp.out[1] = si;
+        qp.out[2] = dr;
+        qp.out[3] = di;
+        qp.out[4] = z;
+        qp.out[5] = qp.energy + z * (sr - qp.vxc);
+    }
+}
+
 // Sum rows of W doubles: block b takes rows [b*chunk, (b+1)*chunk), thread
 // t rows t, t+256, ... of it (coalesced: neighbouring threads read
 // neighbouring rows), then a fixed wave/workgroup tree.  With final set,
-// writes the result as achtemp/asxtemp instead of a row.
+// writes the result as achtemp/asxtemp instead of a row, and with qp.out
+// set also the quasiparticle quantities (qp_epilogue).
 template <int NW>
 __global__ void __launch_bounds__(kRedThreads)
 reduce_rows(const double *__restrict__ in, long nrows, long chunk, double *__restrict__ out,
-            double2 *__restrict__ ach, double2 *__restrict__ asx, int final_stage)
+            double2 *__restrict__ ach, double2 *__restrict__ asx, int final_stage, QpArgs qp)
 {
     constexpr int W = 4 * NW;
     __shared__ double red[kRedThreads / kWave][W];
+    __shared__ double fin[W];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     const long lo = (long)blockIdx.x * chunk;
     const long hi = lo + chunk < nrows ? lo + chunk : nrows;
@@ -149,17 +180,44 @@ reduce_rows(const double *__restrict__ in, long nrows, long chunk, double *__res
             const int w = threadIdx.x / 4, c = threadIdx.x % 4;
             double *dst = reinterpret_cast<double *>(c < 2 ? ach + w : asx + w);
             dst[c & 1] = s;
+            fin[threadIdx.x] = s;
         }
+    }
+    if (final_stage && qp.out) {  // uniform: kernel arguments
+        __syncthreads();
+        if (threadIdx.x == 0) qp_epilogue<NW>(fin, qp);
     }
 }
 
-__global__ void fill_zero(double2 *a, double2 *b, int nw)
+// Zero outputs of an empty sum (and its quasiparticle quantities: Sigma = 0,
+// Z = 1, E_qp = E - V_xc).
+template <int NW>
+__global__ void fill_zero(double2 *a, double2 *b, QpArgs qp)
 {
+    __shared__ double fin[4 * NW];
     int i = threadIdx.x;
-    if (i < nw) {
+    if (i < NW) {
         a[i] = make_double2(0.0, 0.0);
         b[i] = make_double2(0.0, 0.0);
     }
+    if (i < 4 * NW) fin[i] = 0.0;
+    if (qp.out) {
+        __syncthreads();
+        if (i == 0) qp_epilogue<NW>(fin, qp);
+    }
+}
+
+static hipError_t launch_fill_zero(int nw, double2 *a, double2 *b, const QpArgs &qp,
+                                   hipStream_t st)
+{
+    switch (nw) {
+#define GPP_Z(N)                                                                      \
+    case N: hipLaunchKernelGGL(fill_zero<N>, dim3(1), dim3(64), 0, st, a, b, qp); break;
+        GPP_Z(1) GPP_Z(2) GPP_Z(3) GPP_Z(4) GPP_Z(5) GPP_Z(6) GPP_Z(7) GPP_Z(8)
+#undef GPP_Z
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 FwdGeometry fwd_geometry(const Dims32 &d)
@@ -181,7 +239,8 @@ FwdGeometry fwd_geometry(const Dims32 &d)
 
 template <int NW>
 static hipError_t launch_fwd_nw(const Dims32 &d, const FwdGeometry &geo, const DevInputs &in,
-                                double2 *ach, double2 *asx, double *ws, hipStream_t st)
+                                double2 *ach, double2 *asx, double *ws, hipStream_t st,
+                                const QpArgs &qp)
 {
     double *partials = ws;
     double *stage = ws + (size_t)geo.nblocks * 4 * NW;
@@ -192,10 +251,10 @@ static hipError_t launch_fwd_nw(const Dims32 &d, const FwdGeometry &geo, const D
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_rows<NW>, dim3((unsigned)geo.red_blocks), dim3(kRedThreads), 0,
-                       st, partials, geo.nblocks, geo.red_chunk, stage, ach, asx, 0);
+                       st, partials, geo.nblocks, geo.red_chunk, stage, ach, asx, 0, QpArgs());
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_rows<NW>, dim3(1), dim3(kRedThreads), 0, st, stage,
-                       geo.red_blocks, geo.red_blocks, nullptr, ach, asx, 1);
+                       geo.red_blocks, geo.red_blocks, nullptr, ach, asx, 1, qp);
     return hipGetLastError();
 }
 
@@ -212,21 +271,18 @@ static hipError_t launch_reduce_nw(const double *partials, long nrows, double *s
     const long blocks = nrows < kRedBlocks ? nrows : kRedBlocks;
     const long chunk = (nrows + blocks - 1) / blocks;
     hipLaunchKernelGGL(reduce_rows<NW>, dim3((unsigned)blocks), dim3(kRedThreads), 0, st,
-                       partials, nrows, chunk, stage, ach, asx, 0);
+                       partials, nrows, chunk, stage, ach, asx, 0, QpArgs());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_rows<NW>, dim3(1), dim3(kRedThreads), 0, st, stage, blocks,
-                       blocks, nullptr, ach, asx, 1);
+                       blocks, nullptr, ach, asx, 1, QpArgs());
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(int nw, const double *partials, long nrows, double *stage,
                                   double2 *ach, double2 *asx, hipStream_t st)
 {
-    if (nrows <= 0) {
-        hipLaunchKernelGGL(fill_zero, dim3(1), dim3(64), 0, st, ach, asx, nw);
-        return hipGetLastError();
-    }
+    if (nrows <= 0) return launch_fill_zero(nw, ach, asx, QpArgs(), st);
     switch (nw) {
     case 1: return launch_reduce_nw<1>(partials, nrows, stage, ach, asx, st);
     case 2: return launch_reduce_nw<2>(partials, nrows, stage, ach, asx, st);
@@ -241,23 +297,20 @@ hipError_t launch_reduce_partials(int nw, const double *partials, long nrows, do
 }
 
 hipError_t launch_fwd(const Dims32 &d, const DevInputs &in, double2 *ach, double2 *asx,
-                      void *workspace, hipStream_t st)
+                      void *workspace, hipStream_t st, const QpArgs &qp)
 {
     const FwdGeometry geo = fwd_geometry(d);
-    if (geo.nblocks == 0) {
-        hipLaunchKernelGGL(fill_zero, dim3(1), dim3(64), 0, st, ach, asx, d.nw);
-        return hipGetLastError();
-    }
+    if (geo.nblocks == 0) return launch_fill_zero(d.nw, ach, asx, qp, st);
     double *ws = static_cast<double *>(workspace);
     switch (d.nw) {
-    case 1: return launch_fwd_nw<1>(d, geo, in, ach, asx, ws, st);
-    case 2: return launch_fwd_nw<2>(d, geo, in, ach, asx, ws, st);
-    case 3: return launch_fwd_nw<3>(d, geo, in, ach, asx, ws, st);
-    case 4: return launch_fwd_nw<4>(d, geo, in, ach, asx, ws, st);
-    case 5: return launch_fwd_nw<5>(d, geo, in, ach, asx, ws, st);
-    case 6: return launch_fwd_nw<6>(d, geo, in, ach, asx, ws, st);
-    case 7: return launch_fwd_nw<7>(d, geo, in, ach, asx, ws, st);
-    case 8: return launch_fwd_nw<8>(d, geo, in, ach, asx, ws, st);
+    case 1: return launch_fwd_nw<1>(d, geo, in, ach, asx, ws, st, qp);
+    case 2: return launch_fwd_nw<2>(d, geo, in, ach, asx, ws, st, qp);
+    case 3: return launch_fwd_nw<3>(d, geo, in, ach, asx, ws, st, qp);
+    case 4: return launch_fwd_nw<4>(d, geo, in, ach, asx, ws, st, qp);
+    case 5: return launch_fwd_nw<5>(d, geo, in, ach, asx, ws, st, qp);
+    case 6: return launch_fwd_nw<6>(d, geo, in, ach, asx, ws, st, qp);
+    case 7: return launch_fwd_nw<7>(d, geo, in, ach, asx, ws, st, qp);
+    case 8: return launch_fwd_nw<8>(d, geo, in, ach, asx, ws, st, qp);
     default: return hipErrorInvalidValue;
     }
 }

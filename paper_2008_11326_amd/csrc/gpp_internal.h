@@ -40,6 +40,15 @@ struct BwdGeometry {
     size_t workspace_bytes = 0;
 };
 
+// The quasiparticle epilogue of the final reduction stage (gpp_sigma_qp):
+// out = device double[6] or nullptr (plain forward); step = spacing of the
+// frequencies, energy = E of the middle one, vxc = the exchange-correlation
+// value subtracted in the linearised quasiparticle equation.
+struct QpArgs {
+    double *out = nullptr;
+    double step = 0.0, energy = 0.0, vxc = 0.0;
+};
+
 struct BwdOutputs {
     double2 *grad_am, *grad_an, *grad_ieps, *grad_wt;  // NULL = not wanted
 };
@@ -134,6 +143,6 @@ size_t reduce_stage_bytes(int nw, long nrows);
 hipError_t launch_reduce_partials(int nw, const double *partials, long nrows, double *stage,
                                   double2 *ach, double2 *asx, hipStream_t st);
 hipError_t launch_fwd(const Dims32 &d, const DevInputs &in, double2 *ach, double2 *asx,
-                      void *workspace, hipStream_t st);
+                      void *workspace, hipStream_t st, const QpArgs &qp = QpArgs());
 
 }  // namespace gpp

@@ -71,3 +71,31 @@ def mixed_pole_problem(seed, dims, frac):
     pole = low & ~tiny & (rng.random(wt.shape) < 0.2)
     wt.real[pole] = rng.choice(prob.wx_array.ravel(), size=int(pole.sum()))
     return prob
+
+
+def qp_bounds(ach, asx, ach_abs, asx_abs, freq_step, vxc, z, sigma_mid):
+    """Error bounds for the quasiparticle quantities (Sigma re/im, dSigma/dE
+    re/im, Z, E_qp) that follow from the per-output parity bar: each
+    Sigma(E_w) = achtemp[w] - asxtemp[w] may be off by RTOL times the sum of
+    its parts' moduli (their sums of |term| where a part is 0); the central
+    difference divides two of those by 2 freq_step; Z = 1/(1 - Re dSigma)
+    moves by Z^2 times that; E_qp by the change of Z times |Re Sigma - V_xc|
+    plus Z times the error of Sigma.  A few ulp of the epilogue's own
+    arithmetic are added to each."""
+    ach, asx = np.asarray(ach), np.asarray(asx)
+    part = lambda v, s: np.where(np.abs(v) > 0, np.abs(v), np.asarray(s))
+    eps = RTOL * (part(ach, ach_abs) + part(asx, asx_abs))
+    m = (len(ach) - 1) // 2
+    ulp = 8 * np.finfo(float).eps
+    t_sig = eps[m] + ulp * abs(sigma_mid)
+    t_d = (eps[m + 1] + eps[m - 1]) / (2 * freq_step)
+    t_d += ulp * (abs(ach[m + 1] - asx[m + 1]) + abs(ach[m - 1] - asx[m - 1])) / (2 * freq_step)
+    t_z = 2 * z * z * t_d + ulp * abs(z)
+    t_e = t_z * abs(sigma_mid.real - vxc) + abs(z) * t_sig + ulp * (abs(z * (sigma_mid.real - vxc)) + 1)
+    return np.array([t_sig, t_sig, t_d, t_d, t_z, t_e])
+
+
+def qp_vector(q):
+    """The oracle's quasiparticle dict as the library's qp[6] layout."""
+    return np.array([q["sigma"].real, q["sigma"].imag, q["dsigma"].real, q["dsigma"].imag,
+                     q["z"], q["e_qp"]])

@@ -270,3 +270,32 @@ def test_no_device_is_unsupported(lib):
     assert lib.gpp_mb_copy(C.c_void_p(FAKE), C.c_void_p(FAKE + 0x100000), 4096, 1, None) == 5
     assert lib.gpp_mb_read(C.c_void_p(FAKE), 4096, 0, 1, 1, C.c_void_p(FAKE + 0x100000),
                            None) == 5
+
+
+def _qp(lib, dims, ins=None, step=0.5, energy=0.1, vxc=0.0, qp=FAKE + 0xC00000,
+        ws=FAKE + 0x700000, ws_bytes=None):
+    ins = _inputs() if ins is None else ins
+    need = lib.gpp_sigma_fwd_workspace(C.byref(dims))
+    ws_bytes = need if ws_bytes is None else ws_bytes
+    return lib.gpp_sigma_qp(C.byref(dims), C.byref(ins), step, energy, vxc,
+                            C.c_void_p(FAKE + 0x600000), C.c_void_p(FAKE + 0x600100),
+                            C.c_void_p(qp), C.c_void_p(ws), ws_bytes, None)
+
+
+def test_qp_validation(lib):
+    for nw in (1, 2, 4, 8):
+        assert _qp(lib, _dims(nw=nw)) == 1
+        assert "odd" in lib.gpp_last_error().decode()
+    inf, nan = float("inf"), float("nan")
+    for step in (0.0, -0.5, inf, nan):
+        assert _qp(lib, _dims(), step=step) == 1
+        assert "freq_step" in lib.gpp_last_error().decode()
+    for e, v in ((nan, 0.0), (0.0, inf), (-inf, 0.0)):
+        assert _qp(lib, _dims(), energy=e, vxc=v) == 1
+    assert _qp(lib, _dims(), qp=0) == 1 and "qp" in lib.gpp_last_error().decode()
+    assert _qp(lib, _dims(), qp=FAKE + 4) == 1
+    assert _qp(lib, _dims(), ins=_inputs(aqsntemp=0)) == 1
+    assert _qp(lib, _dims(), ws=0) == 4
+    assert _qp(lib, _dims(nw=5), ws_bytes=lib.gpp_sigma_fwd_workspace(C.byref(_dims(nw=5))) - 1) == 4
+    if _hip_device_count() == 0:
+        assert _qp(lib, _dims(nw=5)) == 5

@@ -10,8 +10,8 @@ import pytest
 
 import oracle
 from paper_2008_11326_amd import inputs as I
-from tests.gpu_helpers import (GOLDEN, assert_parity, load_golden, mixed_pole_problem, say,
-                               to_device)
+from tests.gpu_helpers import (GOLDEN, assert_parity, load_golden, mixed_pole_problem,
+                               qp_bounds, qp_vector, say, to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -150,10 +150,25 @@ def test_full_size_against_golden(gpp, key):
     rec = load_golden(key)
     if rec is None:
         pytest.skip(f"tests/golden/fwd_{key}.json not generated")
+    import torch
     wl = I.WORKLOADS[key]
     say(f"[fwd] full size {wl.name}: generating inputs")
     prob = I.make_problem(wl.dims, wl.seed, wl.pole_fraction)
-    ach, asx = run(gpp, prob)
+    d = to_device(prob)
+    ach, asx = gpp.sigma_fwd(**d, nvband=prob.dims.nvband)
+    # the quasiparticle step on the same inputs (gpp_sigma_qp)
+    vxc = -0.25
+    qa, qs, qp = gpp.sigma_qp(**d, nvband=prob.dims.nvband, freq_step=prob.freq_step,
+                              energy=prob.e_lk, vxc=vxc)
+    torch.cuda.synchronize()
+    ach, asx = ach.cpu().numpy(), asx.cpu().numpy()
     e1 = assert_parity(ach, rec["ach"], rec["ach_abs_sum"], key + " achtemp")
     e2 = assert_parity(asx, rec["asx"], rec["asx_abs_sum"], key + " asxtemp")
-    say(f"[fwd] {key} max rel err {max(e1, e2):.2e}")
+    assert np.array_equal(qa.cpu().numpy(), ach) and np.array_equal(qs.cpu().numpy(), asx)
+    q = oracle.quasiparticle(rec["ach"], rec["asx"], prob.freq_step, energy=prob.e_lk, vxc=vxc)
+    tol = qp_bounds(rec["ach"], rec["asx"], rec["ach_abs_sum"], rec["asx_abs_sum"],
+                    prob.freq_step, vxc, q["z"], q["sigma"])
+    err = np.abs(qp.cpu().numpy() - qp_vector(q))
+    assert np.all(err <= tol), (qp.cpu().numpy(), qp_vector(q), tol)
+    say(f"[fwd] {key} max rel err {max(e1, e2):.2e}; quasiparticle error/bound "
+        f"{np.max(err / tol):.2e}")

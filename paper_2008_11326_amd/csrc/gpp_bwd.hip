@@ -18,17 +18,27 @@
 //   daqsmtemp[n][p] = sum_g vcoul[g] e aqsntemp[n][g] conj(Z)
 // with M = aqsntemp[n][g] conj(aqsmtemp[n][p]).
 //
-// Kernels: bwd_pairs (lane = g, wave-uniform p, bands serial) writes
-// dwtilde and dI_eps and, per workgroup of 256 rows, partial sums of
-// daqsmtemp.  Slabs of unoccupied bands form K and L from four factored
-// sums per band (see the slab loop); occupied bands and ragged slabs form
-// u and u^2 per term.  The per-lane daqsmtemp terms of kSlab bands are parked in a
-// per-wave LDS slab and summed together (8 lanes per band, then a DPP sum
-// over the 8), instead of one 64-lane shuffle reduction per band.
-// bwd_bands (lane = g, a wave owns kBandTile bands and walks every p)
-// writes daqsntemp; reduce_am sums the daqsmtemp partials in a fixed order
-// and zero-fills columns >= ngpown.  No atomics: results are bitwise
-// reproducible.
+// Kernels.  bwd_pairs (lane = g, wave-uniform p, bands serial) writes
+// dwtilde and dI_eps.  K and L are linear in ga/2, so over unoccupied bands
+// (with at most four frequencies) the lane never forms them: it keeps four
+// sums per frequency over the bands, weighted by conj(M),
+//   A2_w = sum_n conj(M) r,           B1_w = sum_n conj(M) x r,
+//   B2_w = sum_n conj(M) x r^2,       B3_w = sum_n conj(M) x (x - Re om) r^2
+// (r the reciprocal of |x - om|^2 on branch-A terms, which add nothing
+// otherwise) and applies ga/2 once at the end: with u = (x - om) r and, on
+// branch A, |x - om|^2 r = 1,
+//   sum_n conj(M) K = sum_w ga_w/2 (B1_w - om A2_w),
+//   sum_n conj(M) L = sum_w ga_w/2 (B1_w - 2 (Im om)^2 B2_w - 2i Im om B3_w).
+// Occupied bands, a ragged tail and more frequencies form K and L per band.
+// bwd_bands (lane = g; a workgroup of four waves owns kBandTile bands and
+// 256 consecutive rows, 64 per wave, and walks a range of G' columns)
+// forms vcoul conj(e) Z per term, adds aqsmtemp[n][p] times it into
+// daqsntemp (registers), and takes aqsntemp[n][g] conj(vcoul conj(e) Z) =
+// vcoul e aqsntemp conj(Z) as the term of daqsmtemp[n][p]: those terms go
+// through a per-wave LDS slab (8 lanes per row, then a DPP sum over the 8),
+// are added over the workgroup's four waves and written as one partial per
+// 256-row block; reduce_am sums the partials in a fixed order and zero-fills
+// columns >= ngpown.  No atomics: results are bitwise reproducible.
 #include "gpp_device.h"
 #include "gpp_internal.h"
 
@@ -36,31 +46,39 @@ namespace gpp {
 
 constexpr int kBwdWaves = 4;
 constexpr int kBwdThreads = kBwdWaves * kWave;
-constexpr int kRowsPerBlock = kBwdWaves * kWave;  // g rows per pairs workgroup
-// Bands per batch-inverted group: 3, or 1 with more than four frequencies,
-// so that a group never holds more than 12 denominators (the range for
-// which batch_reciprocal's (Im om)^2 >= 2^-60 lane test keeps every prefix
-// product normal).
+constexpr int kRowsPerBlock = kBwdWaves * kWave;  // g rows per workgroup (both kernels)
+// Bands per batch-inverted group of the per-band forms: 3, or 1 with more
+// than four frequencies, so that a group never holds more than 12
+// denominators (the range for which batch_reciprocal's (Im om)^2 >= 2^-60
+// lane test keeps every prefix product normal).
 constexpr int bwd_group(int nw) { return nw <= 4 ? 3 : 1; }
-constexpr int kChunk = 48;                         // bands per LDS flush (multiple of kSlab)
-constexpr int kSlab = 6;                           // bands per in-wave transpose (two groups)
-constexpr int kOctet = 8;                          // lanes that share one band's row sum
-// Minimum waves per SIMD the compiler must allow (register cap) for the
-// pairs and bands kernels; 1 leaves the allocation to the compiler.  Pairs:
-// 3 waves (up to 168 VGPRs; the factored slab loop needs about 160, and a
-// 4-wave cap spills it, 5-6 % slower on the nb256/ng16384/np819 adjoint
-// workload).  Bands: 5 waves = 96 VGPRs, about 1.3 % faster there than the
-// compiler's own choice.
-#ifndef GPP_BWD_PAIRS_WAVES
-#define GPP_BWD_PAIRS_WAVES 3
+// The pairs kernel's band-sum form: frequencies it takes, and bands per
+// batch-inverted group there (at most 12 / 4 = 3).
+constexpr int kPairsSumsMaxNW = 4;
+#ifndef GPP_BWD_PAIRS_GROUP
+#define GPP_BWD_PAIRS_GROUP 2
 #endif
+constexpr int kPairsGroup = GPP_BWD_PAIRS_GROUP;
+static_assert(kPairsGroup * kPairsSumsMaxNW <= 12, "pairs groups hold at most 12 denominators");
+constexpr int kOctet = 8;                          // lanes that share one row sum
+// Minimum waves per SIMD the compiler must allow (register cap): pairs with
+// at most three frequencies (128 VGPRs; more frequencies take 3 waves, as
+// their band sums need more registers), and the bands kernel without and
+// with the daqsmtemp sums.
+#ifndef GPP_BWD_PAIRS_WAVES
+#define GPP_BWD_PAIRS_WAVES 4
+#endif
+constexpr int pairs_waves(int nw) { return nw <= 3 ? GPP_BWD_PAIRS_WAVES : 3; }
 #ifndef GPP_BWD_BANDS_WAVES
 #define GPP_BWD_BANDS_WAVES 5
+#endif
+#ifndef GPP_BWD_BANDS_AM_WAVES
+#define GPP_BWD_BANDS_AM_WAVES 4
 #endif
 #ifndef GPP_BWD_BAND_TILE
 #define GPP_BWD_BAND_TILE 3
 #endif
-constexpr int kBandTile = GPP_BWD_BAND_TILE;       // bands per bands-kernel wave
+constexpr int kBandTile = GPP_BWD_BAND_TILE;       // bands per bands-kernel workgroup
 // Bands-kernel p-range split (see bwd_geometry): resident bands waves of the
 // MI355X (256 CUs x 4 SIMDs x GPP_BWD_BANDS_WAVES), rounds of them to aim
 // at, and the shortest segment.
@@ -72,6 +90,13 @@ constexpr int kBandsRounds = GPP_BWD_BANDS_ROUNDS;
 constexpr int kMinSegCols = 64;
 static_assert(kBandTile % bwd_group(1) == 0 && kBandTile % bwd_group(8) == 0,
               "band tile must be whole groups");
+// daqsmtemp sums of the bands kernel: the slab holds the terms of two G'
+// columns (kBandTile rows each); every kAmCols columns (even) the four
+// waves' row sums are added and written.
+constexpr int kSlabRows = 2 * kBandTile;
+constexpr int kAmCols = 16;
+constexpr int kAmRows = kBandTile * kAmCols;
+static_assert(kSlabRows <= kOctet && kAmCols % 2 == 0, "slab layout");
 
 // Upstream gradient scaled for the kernels: gh[w] = ga[w]/2 and
 // xgh[w][n] = wx[w][n] ga[w]/2, written once by bwd_prepare.
@@ -92,8 +117,10 @@ __global__ void bwd_prepare(int nb, int nw, const double *__restrict__ wx,
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    // every source lane of the controls used here exists, so no lane keeps
+    // an old value (bound_ctrl only matters for lanes outside the row)
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -192,35 +219,6 @@ __device__ __forceinline__ void sx_band_kl(int n, int nb, const double *__restri
     }
 }
 
-// Batch-inverted reciprocals of the BU*NW terms of BU bands starting at
-// band n for one lane, dr = x - Re om and the denominators dc.  With MASK
-// the reciprocals of terms off branch A are cleared (mask_keep); without
-// it the caller applies the branch itself (dc against the threshold).
-template <int NW, int BU, bool MASK = true>
-__device__ __forceinline__ void group_reciprocals(int n, int nb, const double *__restrict__ wx,
-                                                  double a, double wi2, double thr, bool wide,
-                                                  double (&r)[BU * NW], double (&drs)[BU * NW],
-                                                  double (&dc)[BU * NW])
-{
-    constexpr int Kt = BU * NW;
-    bool isA[Kt];
-#pragma unroll
-    for (int u = 0; u < BU; ++u)
-#pragma unroll
-        for (int w = 0; w < NW; ++w) drs[u * NW + w] = wx[(size_t)w * nb + n + u] - a;
-#pragma unroll
-    for (int k = 0; k < Kt; ++k) {
-        const double wd = fma(drs[k], drs[k], wi2);
-        isA[k] = wd > thr;
-        dc[k] = wd;  // unclamped: see batch_reciprocal
-    }
-    batch_reciprocal<Kt>(dc, r, wide);
-    if (MASK) {
-#pragma unroll
-        for (int k = 0; k < Kt; ++k) r[k] = mask_keep(isA[k], r[k]);
-    }
-}
-
 struct PairState {
     double a, b, wi2, wtr, thr;
     double b2, wi2x2;  // 2 Im om and 2 (Im om)^2
@@ -247,211 +245,200 @@ __device__ __forceinline__ PairState load_pair(const double2 *wt, const double2 
     return s;
 }
 
-// ---- pairs kernel: dwtilde, dI_eps and daqsmtemp partials -----------------
+// One branch-A term of the pairs kernel's band sums: A2 += cM r,
+// B1 += cM x r, B2 += cM x r^2, B3 += cM x dr r^2 (dr = x - Re om), with
+// the compare d > thr as the execution mask (a term off branch A adds
+// nothing, whatever its reciprocal).
+__device__ __forceinline__ void pairs_term(double d, double thr, double r, double x, double dr,
+                                           cplx cm, cplx &A2, cplx &B1, cplx &B2, cplx &B3)
+{
+#if GPP_EXEC_MASK == 2
+    unsigned long long saved;
+    double xr, xr2, xdr2;
+    asm("s_mov_b64 %[sv], exec\n\t"
+        "v_cmpx_gt_f64_e32 vcc, %[d], %[thr]\n\t"
+        "v_mul_f64 %[xr], %[r], %[x]\n\t"
+        "v_fma_f64 %[a2r], %[r], %[cr], %[a2r]\n\t"
+        "v_fma_f64 %[a2i], %[r], %[ci], %[a2i]\n\t"
+        "v_mul_f64 %[xr2], %[xr], %[r]\n\t"
+        "v_fma_f64 %[b1r], %[xr], %[cr], %[b1r]\n\t"
+        "v_fma_f64 %[b1i], %[xr], %[ci], %[b1i]\n\t"
+        "v_mul_f64 %[xdr2], %[xr2], %[dr]\n\t"
+        "v_fma_f64 %[b2r], %[xr2], %[cr], %[b2r]\n\t"
+        "v_fma_f64 %[b2i], %[xr2], %[ci], %[b2i]\n\t"
+        "v_fma_f64 %[b3r], %[xdr2], %[cr], %[b3r]\n\t"
+        "v_fma_f64 %[b3i], %[xdr2], %[ci], %[b3i]\n\t"
+        "s_mov_b64 exec, %[sv]"
+        : [sv] "=&s"(saved), [xr] "=&v"(xr), [xr2] "=&v"(xr2), [xdr2] "=&v"(xdr2),
+          [a2r] "+v"(A2.re), [a2i] "+v"(A2.im), [b1r] "+v"(B1.re), [b1i] "+v"(B1.im),
+          [b2r] "+v"(B2.re), [b2i] "+v"(B2.im), [b3r] "+v"(B3.re), [b3i] "+v"(B3.im)
+        : [d] "v"(d), [thr] "v"(thr), [r] "v"(r), [x] "s"(x), [dr] "v"(dr), [cr] "v"(cm.re),
+          [ci] "v"(cm.im)
+        : "vcc");
+#else
+    const double rm = mask_keep(d > thr, r);
+    const double xr = rm * x, xr2 = xr * rm, xdr2 = xr2 * dr;
+    A2.re = fma(rm, cm.re, A2.re);
+    A2.im = fma(rm, cm.im, A2.im);
+    B1.re = fma(xr, cm.re, B1.re);
+    B1.im = fma(xr, cm.im, B1.im);
+    B2.re = fma(xr2, cm.re, B2.re);
+    B2.im = fma(xr2, cm.im, B2.im);
+    B3.re = fma(xdr2, cm.re, B3.re);
+    B3.im = fma(xdr2, cm.im, B3.im);
+#endif
+}
+
+// G unoccupied bands n .. n+G-1 of one lane into the band sums: one batch
+// inversion over the G*NW denominators, then pairs_term per term.
+template <int NW, int G>
+__device__ __forceinline__ void pairs_sums_group(int n, int nb, int ng, gptr<double2> aqsn,
+                                                 uint32_t goff, gptr<double2> am_col,
+                                                 gptr<double> wx, const PairState &ps,
+                                                 cplx (&A2)[NW], cplx (&B1)[NW],
+                                                 cplx (&B2)[NW], cplx (&B3)[NW])
+{
+    constexpr int Kt = G * NW;
+    double xs[Kt], drs[Kt], dc[Kt], r[Kt];
+    // the group's aqsntemp and aqsmtemp loads go first, so that their
+    // latency overlaps the reciprocal chain
+    cplx an[G], am[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        an[u] = load_row_elem(aqsn + (size_t)(n + u) * ng, ng, goff);
+        am[u] = cload(am_col + (size_t)(n + u) * ng);
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
+#pragma unroll
+    for (int k = 0; k < Kt; ++k) {
+        drs[k] = xs[k] - ps.a;
+        dc[k] = fma(drs[k], drs[k], ps.wi2);  // unclamped: see batch_reciprocal
+    }
+    batch_reciprocal<Kt>(dc, r, ps.wide);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const cplx cM = cmul_conj(am[u], an[u]);  // conj(M) = conj(an) am
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int k = u * NW + w;
+            pairs_term(dc[k], ps.thr, r[k], xs[k], drs[k], cM, A2[w], B1[w], B2[w], B3[w]);
+        }
+    }
+}
+
+// Bands [n, n_end) of one lane in the per-band form: K and L (and, for
+// occupied bands, KS and LS) per band, then Ge += conj(M) Z and
+// Gw += conj(M) W.
+template <int NW>
+__device__ __forceinline__ void pairs_per_band(int n, int n_end, int nb, int nv, int ng,
+                                               const double2 *__restrict__ aqsn,
+                                               const double2 *__restrict__ am_col,
+                                               const double *__restrict__ wx,
+                                               const double2 *__restrict__ gh,
+                                               const double2 *__restrict__ xgh,
+                                               const double2 *__restrict__ gs,
+                                               const PairState &ps, uint32_t goff, cplx &Ge,
+                                               cplx &Gw)
+{
+    constexpr int G = bwd_group(NW);
+    const cplx cw = cmake(ps.om.re, -ps.om.im);  // conj(om)
+    while (n < n_end) {
+        // bands n .. n+cnt-1 form one batch-inverted group
+        const bool occ = n < nv;
+        const int cnt = (!occ && n + G <= n_end) ? G : 1;
+        cplx K[G], L[G];
+        if (cnt == G) {
+            ch_bands_kl<NW, G, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr, ps.wide, K,
+                                     L);
+        } else {
+            cplx K1[1], L1[1];
+            ch_bands_kl<NW, 1, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr, ps.wide, K1,
+                                     L1);
+            K[0] = K1[0];
+            L[0] = L1[0];
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            if (u >= cnt) break;  // wave-uniform
+            const int nn = n + u;
+            cplx Z = cmul(cw, K[u]);
+            cplx W = L[u];
+            if (nn < nv) {
+                cplx KS, LS;
+                sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS, LS);
+                Z = cadd(Z, KS);
+                W = cadd(W, LS);
+            }
+            const cplx an = load_row_elem(as_global(aqsn) + (size_t)nn * ng, ng, goff);
+            const cplx am = cload(am_col + (size_t)nn * ng);
+            const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
+            cmac(Ge, cM, Z);
+            cmac(Gw, cM, W);
+        }
+        n += cnt;
+    }
+}
+
+// ---- pairs kernel: dwtilde and dI_eps -------------------------------------
+// Workgroup = 256 rows (one 64-row tile per wave) x one G' column p, p
+// fastest, so concurrently resident workgroups share one row block.
 template <int NW>
 __global__ void __launch_bounds__(kBwdThreads)
-__attribute__((amdgpu_waves_per_eu(GPP_BWD_PAIRS_WAVES)))
+__attribute__((amdgpu_waves_per_eu(pairs_waves(NW))))
 bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restrict__ aqsm,
           const double2 *__restrict__ aqsn, const double2 *__restrict__ ieps,
           const double2 *__restrict__ wt, const double *__restrict__ vcoul,
           const double *__restrict__ wx, const double2 *__restrict__ gh,
           const double2 *__restrict__ xgh, const double2 *__restrict__ gs,
-          double2 *__restrict__ grad_wt, double2 *__restrict__ grad_ieps,
-          double2 *__restrict__ am_part)
+          double2 *__restrict__ grad_wt, double2 *__restrict__ grad_ieps)
 {
-    // Per-wave transpose slab for the daqsmtemp terms of up to kSlab bands
-    // (8 rows so that every lane's read below stays inside its wave's slab),
-    // and per-wave band sums awaiting the workgroup flush.
-    __shared__ double2 slab[kBwdWaves][kOctet][kWave];
-    __shared__ double2 red[kBwdWaves][kChunk];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const long blk = xcd_remap(blockIdx.x, gridDim.x);
-    if (blk >= nblocks) return;  // whole workgroup leaves together
-    // p fastest: concurrently resident workgroups share one 256-row block
+    if (blk >= nblocks) return;  // no barriers in this kernel
     const int gb = (int)(blk / np);
     const int p = (int)(blk - (long)gb * np);
     const int g = gb * kRowsPerBlock + wid * kWave + lane;
     const bool valid = g < ng;
     const int gc = valid ? g : ng - 1;
     const PairState ps = load_pair(wt, ieps, vcoul, p, ng, gc, valid);
-    const cplx cw = cmake(ps.om.re, -ps.om.im);  // conj(om)
     const double2 *am_col = aqsm + p;
     const uint32_t goff = (uint32_t)gc * (uint32_t)sizeof(double2);
-    // transpose roles: lane = (band j of the slab, segment k of 8 lanes)
-    const int tj = lane >> 3, tk = lane & (kOctet - 1);
 
     cplx Ge = cmake(0.0, 0.0), Gw = cmake(0.0, 0.0);
-    for (int c0 = 0; c0 < nb; c0 += kChunk) {
-        const int c1 = c0 + kChunk < nb ? c0 + kChunk : nb;
-        for (int b0 = c0; b0 < c1; b0 += kSlab) {
-            const int b1 = b0 + kSlab < c1 ? b0 + kSlab : c1;
-            int n = b0;
-            if (b0 >= nv && b1 - b0 == kSlab) {
-                // A whole slab of unoccupied bands: no exchange terms, whole
-                // groups, and K, L from factored sums.  With r_w the masked
-                // reciprocal of |x_w - om|^2 and dr_w = x_w - Re om, every
-                // branch-A term has |x_w - om|^2 r_w = 1, so
-                //   u_w^2 = r_w - 2 (Im om)^2 r_w^2 - 2i (Im om) dr_w r_w^2,
-                //   K = S - om R,  L = S - 2 (Im om)^2 T - 2i (Im om) U,
-                //   S = sum_w xgh_w r_w,  R = sum_w gh_w r_w,
-                //   T = sum_w xgh_w r_w^2,  U = sum_w xgh_w dr_w r_w^2:
-                // four complex-by-real multiply-adds per term.
-#pragma unroll 1
-                for (int q0 = 0; q0 < kSlab; q0 += bwd_group(NW)) {
-                    constexpr int Kt = bwd_group(NW) * NW;
-                    double r[Kt], drs[Kt], dcs[Kt];
-                    const int ng0 = opaque_uniform(__builtin_amdgcn_readfirstlane(b0 + q0));
-                    group_reciprocals<NW, bwd_group(NW), GPP_EXEC_MASK != 2>(
-                        ng0, nb, wx, ps.a, ps.wi2, ps.thr, ps.wide, r, drs, dcs);
+    // occupied bands
+    const int nocc = nv < nb ? nv : nb;
+    pairs_per_band<NW>(0, nocc, nb, nv, ng, aqsn, am_col, wx, gh, xgh, gs, ps, goff, Ge, Gw);
+    int n = nocc;
+    if constexpr (NW <= kPairsSumsMaxNW) {
+        cplx A2[NW], B1[NW], B2[NW], B3[NW];
 #pragma unroll
-                    for (int u = 0; u < bwd_group(NW); ++u) {
-                        const int nn = ng0 + u;
-                        cplx S = cmake(0.0, 0.0), R = S, T = S, U = S;
+        for (int w = 0; w < NW; ++w) A2[w] = B1[w] = B2[w] = B3[w] = cmake(0.0, 0.0);
+        for (; n + kPairsGroup <= nb; n += kPairsGroup)
+            pairs_sums_group<NW, kPairsGroup>(opaque_uniform(n), nb, ng, as_global(aqsn), goff,
+                                              as_global(am_col), as_global(wx), ps, A2, B1, B2,
+                                              B3);
+        // sum_n conj(M) K and sum_n conj(M) L from the band sums
+        cplx SK = cmake(0.0, 0.0), SL = cmake(0.0, 0.0);
 #pragma unroll
-                        for (int w = 0; w < NW; ++w) {
-                            const int k = u * NW + w;
-                            const cplx g = cload(gh + w);
-                            const cplx xg = cload(xgh + (size_t)w * nb + nn);
-#if GPP_EXEC_MASK == 2
-                            if (w > 0) {
-                                // later frequencies add under an execution
-                                // mask written by the branch-A compare
-                                unsigned long long saved;
-                                double q, dq;
-                                asm("s_mov_b64 %[sv], exec\n\t"
-                                    "v_cmpx_gt_f64_e32 vcc, %[d], %[thr]\n\t"
-                                    "v_mul_f64 %[q], %[r], %[r]\n\t"
-                                    "v_fma_f64 %[sr], %[r], %[xr], %[sr]\n\t"
-                                    "v_fma_f64 %[si], %[r], %[xi], %[si]\n\t"
-                                    "v_fma_f64 %[rr], %[r], %[gr], %[rr]\n\t"
-                                    "v_fma_f64 %[ri], %[r], %[gi], %[ri]\n\t"
-                                    "v_mul_f64 %[dq], %[dr], %[q]\n\t"
-                                    "v_fma_f64 %[tr], %[q], %[xr], %[tr]\n\t"
-                                    "v_fma_f64 %[ti], %[q], %[xi], %[ti]\n\t"
-                                    "v_fma_f64 %[ur], %[dq], %[xr], %[ur]\n\t"
-                                    "v_fma_f64 %[ui], %[dq], %[xi], %[ui]\n\t"
-                                    "s_mov_b64 exec, %[sv]"
-                                    : [sv] "=&s"(saved), [q] "=&v"(q), [dq] "=&v"(dq),
-                                      [sr] "+v"(S.re), [si] "+v"(S.im), [rr] "+v"(R.re),
-                                      [ri] "+v"(R.im), [tr] "+v"(T.re), [ti] "+v"(T.im),
-                                      [ur] "+v"(U.re), [ui] "+v"(U.im)
-                                    : [d] "v"(dcs[k]), [thr] "v"(ps.thr), [r] "v"(r[k]),
-                                      [dr] "v"(drs[k]), [xr] "s"(xg.re), [xi] "s"(xg.im),
-                                      [gr] "s"(g.re), [gi] "s"(g.im)
-                                    : "vcc");
-                                continue;
-                            }
-                            // the first frequency starts the sums through a select
-                            r[k] = mask_keep(dcs[k] > ps.thr, r[k]);
-#endif
-                            const double q = r[k] * r[k];
-                            const double dq = drs[k] * q;
-                            S.re = fma(r[k], xg.re, S.re);
-                            S.im = fma(r[k], xg.im, S.im);
-                            R.re = fma(r[k], g.re, R.re);
-                            R.im = fma(r[k], g.im, R.im);
-                            T.re = fma(q, xg.re, T.re);
-                            T.im = fma(q, xg.im, T.im);
-                            U.re = fma(dq, xg.re, U.re);
-                            U.im = fma(dq, xg.im, U.im);
-                        }
-                        // Z = conj(om) (S - om R),  W = L
-                        const cplx Z = cmake(fma(ps.a, S.re, fma(ps.b, S.im, -ps.wtr * R.re)),
-                                             fma(ps.a, S.im, fma(-ps.b, S.re, -ps.wtr * R.im)));
-                        const cplx W = cmake(fma(ps.b2, U.im, fma(-ps.wi2x2, T.re, S.re)),
-                                             fma(-ps.b2, U.re, fma(-ps.wi2x2, T.im, S.im)));
-                        const cplx an = load_row_elem(as_global(aqsn) + (size_t)nn * ng, ng, goff);
-                        const cplx am = cload(am_col + (size_t)nn * ng);
-                        const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
-                        cmac(Ge, cM, Z);
-                        cmac(Gw, cM, W);
-                        if (am_part) {
-                            const cplx t = cmul(ps.ve, cmul_conj(an, Z));
-                            slab[wid][nn - b0][lane] = make_double2(t.re, t.im);
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                n = b1;
-            }
-            while (n < b1) {
-                // bands n .. n+cnt-1 form one batch-inverted group
-                const bool occ = n < nv;
-                const int cnt = (!occ && n + bwd_group(NW) <= b1) ? bwd_group(NW) : 1;
-                cplx K[bwd_group(NW)], L[bwd_group(NW)];
-                if (cnt == bwd_group(NW)) {
-                    ch_bands_kl<NW, bwd_group(NW), true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2,
-                                                     ps.thr, ps.wide, K, L);
-                } else {
-                    cplx K1[1], L1[1];
-                    ch_bands_kl<NW, 1, true>(n, nb, wx, gh, xgh, ps.a, ps.b, ps.wi2, ps.thr,
-                                             ps.wide, K1, L1);
-                    K[0] = K1[0];
-                    L[0] = L1[0];
-                }
-#pragma unroll
-                for (int u = 0; u < bwd_group(NW); ++u) {
-                    if (u >= cnt) break;  // wave-uniform
-                    const int nn = n + u;
-                    cplx Z = cmul(cw, K[u]);
-                    cplx W = L[u];
-                    if (nn < nv) {
-                        cplx KS, LS;
-                        sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS,
-                                       LS);
-                        Z = cadd(Z, KS);
-                        W = cadd(W, LS);
-                    }
-                    const cplx an = load_row_elem(as_global(aqsn) + (size_t)nn * ng, ng, goff);
-                    const cplx am = cload(am_col + (size_t)nn * ng);
-                    const cplx cM = cmul_conj(am, an);  // conj(M) = conj(an) am
-                    cmac(Ge, cM, Z);
-                    cmac(Gw, cM, W);
-                    if (am_part) {
-                        // this lane's term of daqsmtemp[nn][p]: ve an conj(Z)
-                        const cplx t = cmul(ps.ve, cmul_conj(an, Z));
-                        slab[wid][nn - b0][lane] = make_double2(t.re, t.im);
-                    }
-                }
-                n += cnt;
-            }
-            if (am_part) {
-                // Row sums of the slab: lane (tj, tk) adds 8 entries of row tj
-                // (rotated so the 8 lanes of an octet hit distinct banks), then
-                // the octet adds its 8 partial sums.
-                wave_lds_sync();
-                double sr = 0.0, si = 0.0;
-#pragma unroll
-                for (int i = 0; i < kOctet; ++i) {
-                    const double2 v = slab[wid][tj][kOctet * tk + ((i + tk + tj) & (kOctet - 1))];
-                    sr += v.x;
-                    si += v.y;
-                }
-                sr = octet_sum(sr);
-                si = octet_sum(si);
-                if (tk == 0 && tj < b1 - b0) red[wid][b0 - c0 + tj] = make_double2(sr, si);
-                wave_lds_sync();
-            }
+        for (int w = 0; w < NW; ++w) {
+            const cplx h = cload(gh + w);
+            const cplx k = cadd(B1[w], cmul(cmake(-ps.a, -ps.b), A2[w]));  // B1 - om A2
+            // B1 - 2 (Im om)^2 B2 - 2i (Im om) B3
+            const cplx l = cmake(fma(ps.b2, B3[w].im, fma(-ps.wi2x2, B2[w].re, B1[w].re)),
+                                 fma(-ps.b2, B3[w].re, fma(-ps.wi2x2, B2[w].im, B1[w].im)));
+            cmac(SK, h, k);
+            cmac(SL, h, l);
         }
-        if (am_part) {
-            __syncthreads();
-            const int t = threadIdx.x;
-            if (t < 2 * (c1 - c0)) {
-                const int j = t >> 1, c = t & 1;
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < kBwdWaves; ++k) {
-                    const double2 v = red[k][j];
-                    s += c ? v.y : v.x;
-                }
-                double *dst = reinterpret_cast<double *>(
-                    am_part + ((size_t)gb * nb + c0 + j) * np + p);
-                dst[c] = s;
-            }
-            __syncthreads();
-        }
+        cmac(Ge, cmake(ps.om.re, -ps.om.im), SK);
+        Gw = cadd(Gw, SL);
     }
+    // a ragged tail, or every unoccupied band with more frequencies
+    pairs_per_band<NW>(n, nb, nb, nv, ng, aqsn, am_col, wx, gh, xgh, gs, ps, goff, Ge, Gw);
+
     if (valid) {
         const double v = vcoul[g];
         const size_t idx = (size_t)p * ng + g;
@@ -466,22 +453,98 @@ bwd_pairs(int nb, int nv, int ng, int np, long nblocks, const double2 *__restric
     }
 }
 
-// ---- bands kernel: daqsntemp --------------------------------------------
-// Fast form of one wave's p loop: every band n0 .. n0+kBandTile-1 is
+// ---- bands kernel: daqsntemp and the daqsmtemp partials -------------------
+// LDS of one bands workgroup's daqsmtemp sums: each wave's slab of
+// per-lane terms (kBandTile bands x two G' columns) and the waves' row sums
+// of up to kAmCols columns.
+struct AmStage {
+    double2 slab[kBwdWaves][kSlabRows][kWave];
+    double2 red[kBwdWaves][kAmRows];
+};
+
+// Where a bands workgroup's daqsmtemp sums go: the slab row of band u at
+// column p is ((p - p_lo) % 2) kBandTile + u; `chunk` is the first column of
+// the rows waiting in red.
+struct AmCtx {
+    AmStage *st;
+    double2 *part;  // am_part: [256-row block][nb][np]
+    int wid, lane, gblk, n0, nb, np, p_lo, p_hi, chunk;
+};
+
+// This lane's daqsmtemp term of band u at column p: an conj(vcoul conj(e) Z).
+__device__ __forceinline__ void am_put(AmCtx &a, int p, int u, cplx an, cplx vz)
+{
+    const cplx t = cmul_conj(an, vz);
+    a.st->slab[a.wid][((p - a.p_lo) & 1) * kBandTile + u][a.lane] = make_double2(t.re, t.im);
+}
+
+// After column p: when the slab is full (two columns) or p is the range's
+// last column, add each slab row over the wave (lane (tj, tk) adds 8
+// entries of row tj, rotated so the 8 lanes of an octet hit distinct banks,
+// then the octet adds its 8 sums) into red; every kAmCols columns, and at
+// the end, add red over the four waves and write the partials.  Every wave
+// of the workgroup calls this for the same columns.
+__device__ __forceinline__ void am_column_done(AmCtx &a, int p)
+{
+    const int c = (p - a.p_lo) & 1;
+    const bool last = p + 1 == a.p_hi;
+    if (c == 1 || last) {
+        const int rows = (c + 1) * kBandTile;
+        const int base = (p - c - a.chunk) * kBandTile;
+        wave_lds_sync();
+        const int tj = a.lane >> 3, tk = a.lane & (kOctet - 1);
+        double sr = 0.0, si = 0.0;
+        if (tj < rows) {
+#pragma unroll
+            for (int i = 0; i < kOctet; ++i) {
+                const double2 v = a.st->slab[a.wid][tj][kOctet * tk + ((i + tk + tj) & (kOctet - 1))];
+                sr += v.x;
+                si += v.y;
+            }
+        }
+        sr = octet_sum(sr);
+        si = octet_sum(si);
+        if (tk == 0 && tj < rows) a.st->red[a.wid][base + tj] = make_double2(sr, si);
+        wave_lds_sync();
+    }
+    if (p + 1 - a.chunk == kAmCols || last) {
+        __syncthreads();
+        const int rows = (p + 1 - a.chunk) * kBandTile;
+        const int t = threadIdx.x;
+        if (t < 2 * rows) {
+            const int j = t >> 1, comp = t & 1;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBwdWaves; ++k) {
+                const double2 v = a.st->red[k][j];
+                s += comp ? v.y : v.x;
+            }
+            const int col = a.chunk + j / kBandTile, n = a.n0 + j % kBandTile;
+            if (n < a.nb)
+                reinterpret_cast<double *>(a.part + ((size_t)a.gblk * a.nb + n) * a.np + col)[comp] = s;
+        }
+        __syncthreads();
+        a.chunk = p + 1;
+    }
+}
+
+// Fast form of one workgroup's p loop: every band n0 .. n0+kBandTile-1 is
 // unoccupied and below nb.  With u_w = (x_w - om) r_w (r_w the masked
 // reciprocal of |x_w - om|^2),
 //   K = sum_w gh_w u_w = S - om R,  S = sum_w xgh_w r_w,  R = sum_w gh_w r_w,
 // so vcoul conj(e) Z = vcoul conj(e) conj(om) K = c1 S - c2 R with the
 // per-pair constants c1 = vcoul conj(e om) and c2 = vcoul conj(e) |om|^2.
-template <int NW>
-__device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, int n0, int gc,
-                                           double vc,
+template <int NW, bool AM>
+__device__ __forceinline__ void bands_fast(int nb, int ng, int n0, int gc, double vc,
                                            gptr<double2> aqsm, gptr<double2> ieps,
                                            gptr<double2> wt, gptr<double> wx,
                                            gptr<double2> gh, gptr<double2> xgh,
+                                           const cplx (&an)[kBandTile], AmCtx &amc,
                                            cplx (&acc)[kBandTile])
 {
-    constexpr int Kt = bwd_group(NW) * NW;
+    constexpr int G = bwd_group(NW);
+    constexpr int Kt = G * NW;
+    const int p_lo = amc.p_lo, p_hi = amc.p_hi;
     // om and e of the next column are loaded one iteration ahead, so their
     // latency overlaps this column's arithmetic
     cplx om_next = cload(wt + (size_t)p_lo * ng + gc), e_next = cload(ieps + (size_t)p_lo * ng + gc);
@@ -500,12 +563,12 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
         const cplx c1 = cmul(vce, cmake(a, -b));
         const cplx c2 = cscale(wtr, vce);
 #pragma unroll
-        for (int u0 = 0; u0 < kBandTile; u0 += bwd_group(NW)) {
+        for (int u0 = 0; u0 < kBandTile; u0 += G) {
             const int n = nfirst + u0;
             double xs[Kt], dc[Kt], r[Kt];
             bool isA[Kt];
 #pragma unroll
-            for (int u = 0; u < bwd_group(NW); ++u)
+            for (int u = 0; u < G; ++u)
 #pragma unroll
                 for (int w = 0; w < NW; ++w) xs[u * NW + w] = wx[(size_t)w * nb + n + u];
 #pragma unroll
@@ -517,7 +580,7 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
             }
             batch_reciprocal<Kt>(dc, r, wide);
 #pragma unroll
-            for (int u = 0; u < bwd_group(NW); ++u) {
+            for (int u = 0; u < G; ++u) {
 #if GPP_EXEC_MASK == 2
                 // the first frequency starts S and R through a select, the
                 // others add under an execution mask written by the compare
@@ -562,42 +625,44 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int p_lo, int p_hi, i
                                       c1.re * S.im + c1.im * S.re - c2.re * R.im - c2.im * R.re);
                 const cplx am = cload(aqsm + (size_t)(n + u) * ng + p);
                 cmac(acc[u0 + u], am, vZ);
+                if constexpr (AM) am_put(amc, p, u0 + u, an[u0 + u], vZ);
             }
             // one group's reciprocal chain at a time (register pressure)
             __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (AM) am_column_done(amc, p);
     }
 }
 
 // Generic form: occupied bands (exchange terms) and a ragged last tile.
-template <int NW>
-__device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int p_lo, int p_hi, int n0,
-                                              int gc,
-                                              bool valid, const double2 *__restrict__ aqsm,
+template <int NW, bool AM>
+__device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int n0, int gc, bool valid,
+                                              const double2 *__restrict__ aqsm,
                                               const double2 *__restrict__ ieps,
                                               const double2 *__restrict__ wt,
                                               const double *__restrict__ vcoul,
                                               const double *__restrict__ wx,
                                               const double2 *__restrict__ gh,
                                               const double2 *__restrict__ gs,
+                                              const cplx (&an)[kBandTile], AmCtx &amc,
                                               cplx (&acc)[kBandTile])
 {
-    for (int p = p_lo; p < p_hi; ++p) {
+    constexpr int G = bwd_group(NW);
+    for (int p = amc.p_lo; p < amc.p_hi; ++p) {
         const PairState ps = load_pair(wt, ieps, vcoul, p, ng, gc, valid);
         const cplx vce = cmake(ps.ve.re, -ps.ve.im);           // vcoul conj(e)
         const cplx vcw = cmul(vce, cmake(ps.om.re, -ps.om.im));  // vcoul conj(e om)
 #pragma unroll
-        for (int u0 = 0; u0 < kBandTile; u0 += bwd_group(NW)) {
+        for (int u0 = 0; u0 < kBandTile; u0 += G) {
             const int n = n0 + u0;
-            if (n >= nb) break;  // wave-uniform
-            cplx K[bwd_group(NW)], L[bwd_group(NW)];
-            const bool full = n + bwd_group(NW) <= nb && n >= nv;
+            cplx K[G], L[G];
+            const bool full = n + G <= nb && n >= nv;
             if (full) {
-                ch_bands_kl<NW, bwd_group(NW), false>(n, nb, wx, gh, nullptr, ps.a, ps.b, ps.wi2,
-                                                  ps.thr, ps.wide, K, L);
+                ch_bands_kl<NW, G, false>(n, nb, wx, gh, nullptr, ps.a, ps.b, ps.wi2, ps.thr,
+                                          ps.wide, K, L);
             } else {
 #pragma unroll
-                for (int u = 0; u < bwd_group(NW); ++u) {
+                for (int u = 0; u < G; ++u) {
                     K[u] = cmake(0.0, 0.0);
                     if (n + u < nb) {
                         cplx K1[1], L1[1];
@@ -608,11 +673,12 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int p_lo, 
                 }
             }
 #pragma unroll
-            for (int u = 0; u < bwd_group(NW); ++u) {
+            for (int u = 0; u < G; ++u) {
                 const int nn = n + u;
+                cplx vZ = cmake(0.0, 0.0);
                 if (nn < nb) {
                     // vcoul conj(e) Z = vcoul conj(e om) K [+ vcoul conj(e) KS]
-                    cplx vZ = cmul(vcw, K[u]);
+                    vZ = cmul(vcw, K[u]);
                     if (nn < nv) {
                         cplx KS, LS;
                         sx_band_kl<NW>(nn, nb, wx, gs, ps.a, ps.b, ps.wi2, ps.wtr, ps.thr, KS, LS);
@@ -621,50 +687,78 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int p_lo, 
                     const cplx am = cload(aqsm + (size_t)nn * ng + p);
                     cmac(acc[u0 + u], am, vZ);
                 }
+                if constexpr (AM) am_put(amc, p, u0 + u, an[u0 + u], vZ);
             }
         }
+        if constexpr (AM) am_column_done(amc, p);
     }
 }
 
-template <int NW>
+// Workgroup = kBandTile bands x 256 rows (one 64-row tile per wave) x one
+// segment of the G' range; band tile fastest (neighbouring workgroups
+// share the rows of wtilde/I_eps), then row block, then segment.  One
+// segment writes daqsntemp itself, several write partial sums (grad_an may
+// be NULL: daqsmtemp only).  With AM, also the daqsmtemp partials of the
+// workgroup's bands, rows and columns.
+template <int NW, bool AM>
 __global__ void __launch_bounds__(kBwdThreads)
-__attribute__((amdgpu_waves_per_eu(GPP_BWD_BANDS_WAVES)))
-bwd_bands(int nb, int nv, int ng, int np, long ntiles, int nbt, int ngt, int nps,
-          const double2 *__restrict__ aqsm, const double2 *__restrict__ ieps,
-          const double2 *__restrict__ wt, const double *__restrict__ vcoul,
-          const double *__restrict__ wx, const double2 *__restrict__ gh,
-          const double2 *__restrict__ xgh, const double2 *__restrict__ gs,
-          double2 *__restrict__ grad_an)
+__attribute__((amdgpu_waves_per_eu(AM ? GPP_BWD_BANDS_AM_WAVES : GPP_BWD_BANDS_WAVES)))
+bwd_bands(int nb, int nv, int ng, int np, long nwg, int nbt, int ngb, int nps,
+          const double2 *__restrict__ aqsm, const double2 *__restrict__ aqsn,
+          const double2 *__restrict__ ieps, const double2 *__restrict__ wt,
+          const double *__restrict__ vcoul, const double *__restrict__ wx,
+          const double2 *__restrict__ gh, const double2 *__restrict__ xgh,
+          const double2 *__restrict__ gs, double2 *__restrict__ grad_an,
+          double2 *__restrict__ am_part)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const long tile = (long)xcd_remap(blockIdx.x, gridDim.x) * kBwdWaves + wid;
-    if (tile >= ntiles) return;  // wave-uniform; no barriers below
-    // band tile fastest (neighbouring waves share the g rows of wtilde/I_eps),
-    // then g tile, then segment of the p range
-    const long per_seg = (long)ngt * nbt;
-    const int seg = (int)(tile / per_seg);
-    const long in_seg = tile - (long)seg * per_seg;
-    const int gt = (int)(in_seg / nbt);
-    const int n0 = (int)(in_seg - (long)gt * nbt) * kBandTile;
-    const int p_lo = (int)((long)np * seg / nps), p_hi = (int)((long)np * (seg + 1) / nps);
-    // one segment writes the gradient itself, several write partial sums
-    double2 *const dst = grad_an + (size_t)seg * nb * ng;
-    const int g = gt * kWave + lane;
+    const long wg = xcd_remap(blockIdx.x, gridDim.x);
+    if (wg >= nwg) return;  // the whole workgroup leaves together
+    const long per_seg = (long)ngb * nbt;
+    const int seg = (int)(wg / per_seg);
+    const long in_seg = wg - (long)seg * per_seg;
+    const int gblk = (int)(in_seg / nbt);
+    const int n0 = (int)(in_seg - (long)gblk * nbt) * kBandTile;
+    double2 *const dst = grad_an ? grad_an + (size_t)seg * nb * ng : nullptr;
+    const int g = gblk * kRowsPerBlock + wid * kWave + lane;
     const bool valid = g < ng;
     const int gc = valid ? g : ng - 1;
 
+    AmCtx amc;
+    amc.st = nullptr;
+    if constexpr (AM) {
+        __shared__ AmStage stage;
+        amc.st = &stage;
+    }
+    amc.part = am_part;
+    amc.wid = wid;
+    amc.lane = lane;
+    amc.gblk = gblk;
+    amc.n0 = n0;
+    amc.nb = nb;
+    amc.np = np;
+    amc.p_lo = (int)((long)np * seg / nps);
+    amc.p_hi = (int)((long)np * (seg + 1) / nps);
+    amc.chunk = amc.p_lo;
+
+    cplx an[kBandTile];
+#pragma unroll
+    for (int u = 0; u < kBandTile; ++u) {
+        an[u] = cmake(0.0, 0.0);
+        if (AM && n0 + u < nb) an[u] = cload(aqsn + (size_t)(n0 + u) * ng + gc);
+    }
     cplx acc[kBandTile];
 #pragma unroll
     for (int u = 0; u < kBandTile; ++u) acc[u] = cmake(0.0, 0.0);
     if (n0 >= nv && n0 + kBandTile <= nb)
-        bands_fast<NW>(nb, ng, p_lo, p_hi, n0, gc, valid ? vcoul[gc] : 0.0, as_global(aqsm),
-                       as_global(ieps), as_global(wt), as_global(wx), as_global(gh),
-                       as_global(xgh), acc);
+        bands_fast<NW, AM>(nb, ng, n0, gc, valid ? vcoul[gc] : 0.0, as_global(aqsm),
+                           as_global(ieps), as_global(wt), as_global(wx), as_global(gh),
+                           as_global(xgh), an, amc, acc);
     else
-        bands_generic<NW>(nb, nv, ng, p_lo, p_hi, n0, gc, valid, aqsm, ieps, wt, vcoul, wx, gh,
-                          gs, acc);
-    if (valid) {
+        bands_generic<NW, AM>(nb, nv, ng, n0, gc, valid, aqsm, ieps, wt, vcoul, wx, gh, gs, an,
+                              amc, acc);
+    if (dst && valid) {
 #pragma unroll
         for (int u = 0; u < kBandTile; ++u) {
             const int n = n0 + u;
@@ -722,7 +816,7 @@ BwdGeometry bwd_geometry(const Dims32 &d)
         geo.ngb = (d.ng + kRowsPerBlock - 1) / kRowsPerBlock;
         geo.pair_blocks = (long)geo.ngb * d.np;
         geo.nbt = (d.nb + kBandTile - 1) / kBandTile;
-        geo.ngt = (d.ng + kWave - 1) / kWave;
+        geo.ngt = geo.ngb * kBwdWaves;
         // Split the p loop into segments when one pass has too few waves:
         // every wave walks its whole p range, so the last partial round of
         // a short grid leaves most SIMDs idle.  Aim at kBandsRounds rounds
@@ -734,7 +828,7 @@ BwdGeometry bwd_geometry(const Dims32 &d)
         const long max_nps = d.np / kMinSegCols > 1 ? d.np / kMinSegCols : 1;
         geo.nps = (int)(nps < max_nps ? nps : max_nps);
         geo.band_tiles = per_seg * geo.nps;
-        geo.band_blocks = (geo.band_tiles + kBwdWaves - 1) / kBwdWaves;
+        geo.band_blocks = (long)geo.ngb * geo.nbt * geo.nps;
         geo.am_part_elems = (size_t)geo.ngb * d.nb * d.np;
         geo.an_part_elems = geo.nps > 1 ? (size_t)geo.nps * d.nb * d.ng : 0;
     }
@@ -762,32 +856,38 @@ static hipError_t launch_bwd_nw(const Dims32 &d, const BwdGeometry &geo, const D
                        in.wx, ga, gh, xgh);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const bool want_pairs = out.grad_wt || out.grad_ieps || out.grad_am;
-    if (want_pairs) {
+    if (out.grad_wt || out.grad_ieps) {
         hipLaunchKernelGGL(bwd_pairs<NW>, dim3((unsigned)geo.pair_blocks), dim3(kBwdThreads), 0,
                            st, d.nb, d.nv, d.ng, d.np, geo.pair_blocks, in.aqsm, in.aqsn,
                            in.ieps, in.wt, in.vcoul, in.wx, gh, xgh, gs, out.grad_wt,
-                           out.grad_ieps, out.grad_am ? am_part : nullptr);
+                           out.grad_ieps);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (out.grad_an || out.grad_am) {
+        double2 *an_dst = !out.grad_an ? nullptr : (geo.nps > 1 ? an_part : out.grad_an);
+        if (out.grad_am)
+            hipLaunchKernelGGL((bwd_bands<NW, true>), dim3((unsigned)geo.band_blocks),
+                               dim3(kBwdThreads), 0, st, d.nb, d.nv, d.ng, d.np, geo.band_blocks,
+                               geo.nbt, geo.ngb, geo.nps, in.aqsm, in.aqsn, in.ieps, in.wt,
+                               in.vcoul, in.wx, gh, xgh, gs, an_dst, am_part);
+        else
+            hipLaunchKernelGGL((bwd_bands<NW, false>), dim3((unsigned)geo.band_blocks),
+                               dim3(kBwdThreads), 0, st, d.nb, d.nv, d.ng, d.np, geo.band_blocks,
+                               geo.nbt, geo.ngb, geo.nps, in.aqsm, in.aqsn, in.ieps, in.wt,
+                               in.vcoul, in.wx, gh, xgh, gs, an_dst, nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (out.grad_an && geo.nps > 1) {
+            const long nbg = (long)d.nb * d.ng;
+            hipLaunchKernelGGL(reduce_an, dim3((unsigned)((nbg + 255) / 256)), dim3(256), 0, st,
+                               nbg, geo.nps, an_part, out.grad_an);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     if (out.grad_am) {
         const long n = (long)d.nb * d.ng;
         hipLaunchKernelGGL(reduce_am, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d.nb,
                            d.ng, d.np, geo.ngb, am_part, out.grad_am);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (out.grad_an) {
-        double2 *an_dst = geo.nps > 1 ? an_part : out.grad_an;
-        hipLaunchKernelGGL(bwd_bands<NW>, dim3((unsigned)geo.band_blocks), dim3(kBwdThreads), 0,
-                           st, d.nb, d.nv, d.ng, d.np, geo.band_tiles, geo.nbt, geo.ngt, geo.nps,
-                           in.aqsm, in.ieps, in.wt, in.vcoul, in.wx, gh, xgh, gs, an_dst);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (geo.nps > 1) {
-            const long nbg = (long)d.nb * d.ng;
-            hipLaunchKernelGGL(reduce_an, dim3((unsigned)((nbg + 255) / 256)), dim3(256), 0, st,
-                               nbg, geo.nps, an_part, out.grad_an);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
     }
     return hipSuccess;
 }

@@ -112,6 +112,30 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
                          size_t workspace_bytes, void *stream);
 
 /*
+ * gpp_sigma_fwd_noalloc -- gpp_sigma_fwd for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same operation, kernels and results
+ * (bit for bit) as gpp_sigma_fwd; the workspace is a fixed device array of
+ * GPP_NOALLOC_SCRATCH_BYTES inside the library, one per device, allocated
+ * with the library's code object and held until the process ends.  The
+ * call itself allocates nothing: the first call on a device resolves that
+ * device's array address (hipGetSymbolAddress, with the device current),
+ * so make one call before capturing a graph.
+ *   dims, in, achtemp, asxtemp, stream: as gpp_sigma_fwd
+ * Sizes whose gpp_sigma_fwd_workspace(dims) exceeds GPP_NOALLOC_SCRATCH_BYTES
+ * return GPP_ERR_WORKSPACE and enqueue nothing (48 MiB covers 1024 bands x
+ * 65536 rows x 3276 columns at nfreq 3).  Every call on one device shares
+ * that device's array: calls that overlap in time on one device (different
+ * streams, or host threads without ordering) race and give wrong results;
+ * calls ordered on one stream are safe.  Nothing in the array needs to
+ * start at zero (every partial row a kernel reads was written earlier in
+ * the same call).
+ */
+#define GPP_NOALLOC_SCRATCH_BYTES (48u << 20)
+gpp_status gpp_sigma_fwd_noalloc(const gpp_dims *dims, const gpp_inputs *in, double *achtemp,
+                                 double *asxtemp, void *stream);
+
+/*
  * gpp_sigma_qp -- gpp_sigma_fwd followed by the quasiparticle step that
  * consumes its outputs in the Sigma module the kernel comes from (Sec.
  * II-A; the paper does not print this step, so the reading below is the

@@ -24,7 +24,7 @@ import ctypes as C
 from . import _lib
 from ._lib import GppError, MAX_NFREQ
 
-__all__ = ["sigma_fwd", "sigma_qp", "sigma_bwd", "sigma", "GppSigma", "Plan", "sigma_batched",
+__all__ = ["sigma_fwd", "sigma_fwd_noalloc", "sigma_qp", "sigma_bwd", "sigma", "GppSigma", "Plan", "sigma_batched",
            "fwd_workspace_bytes", "bwd_workspace_bytes", "GppError", "MAX_NFREQ",
            "library_path"]
 
@@ -119,6 +119,27 @@ def sigma_fwd(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
                                _ptr(workspace), workspace.numel(),
                                C.c_void_p(stream))
     _lib.check(st, "gpp_sigma_fwd")
+    return ach, asx
+
+
+def sigma_fwd_noalloc(aqsmtemp, aqsntemp, I_eps_array, wtilde_array, vcoul, wx_array,
+                      nvband: int, *, out, stream=None):
+    """sigma_fwd through gpp_sigma_fwd_noalloc, which allocates nothing: its
+    workspace is a fixed array inside the library (include/gpp.h).  `out`
+    must be a pair of preallocated complex128 [nfreq] tensors."""
+    torch = _torch()
+    lib = _lib.load()
+    dims, ins, dev = _prepare(aqsmtemp, aqsntemp, I_eps_array, wtilde_array,
+                              vcoul, wx_array, nvband)
+    ach, asx = out
+    _check_tensor("achtemp", ach, torch.complex128, (dims.nfreq,), dev)
+    _check_tensor("asxtemp", asx, torch.complex128, (dims.nfreq,), dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    with torch.cuda.device(dev):
+        st = lib.gpp_sigma_fwd_noalloc(C.byref(dims), C.byref(ins), _ptr(ach), _ptr(asx),
+                                       C.c_void_p(stream))
+    _lib.check(st, "gpp_sigma_fwd_noalloc")
     return ach, asx
 
 

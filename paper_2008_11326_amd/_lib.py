@@ -18,6 +18,7 @@ GPP_OK = 0
 STATUS = {0: "GPP_OK", 1: "GPP_ERR_INVALID", 2: "GPP_ERR_HIP",
           3: "GPP_ERR_NOMEM", 4: "GPP_ERR_WORKSPACE", 5: "GPP_ERR_UNSUPPORTED"}
 MAX_NFREQ = 8
+NOALLOC_SCRATCH_BYTES = 48 << 20  # GPP_NOALLOC_SCRATCH_BYTES of include/gpp.h
 
 
 class GppError(RuntimeError):
@@ -55,6 +56,8 @@ _SIGNATURES = [
     ("gpp_sigma_fwd", C.c_int,
      [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p,
       C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("gpp_sigma_fwd_noalloc", C.c_int,
+     [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_void_p, C.c_void_p, C.c_void_p]),
     ("gpp_sigma_qp", C.c_int,
      [C.POINTER(GppDims), C.POINTER(GppInputs), C.c_double, C.c_double, C.c_double,
       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),

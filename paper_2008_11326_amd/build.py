@@ -23,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgpp.so")
 SOURCES = ["gpp_api.hip", "gpp_fwd.hip", "gpp_bwd.hip", "gpp_batched.hip", "gpp_plan.hip",
-           "gpp_ladder.hip",
+           "gpp_ladder.hip", "gpp_noalloc.hip",
            "gpp_microbench.hip"]
 HEADERS = ["gpp_device.h", "gpp_fwd_tile.h", "gpp_internal.h"]
 ARCH = "gfx950"

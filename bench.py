@@ -8,7 +8,7 @@ ncouls=65536, ngpown=3276, nfreq=3, 1 % of wtilde planted within 1e-6 of a
 frequency, seed 2; inputs resident in HBM.  Prints one JSON line on stdout.
 
     python bench.py [--steps K] [--warmup W] [--workload large|si|small|adjoint]
-    python bench.py --leg adjoint|batched|si     # one leg alone, for profiling
+    python bench.py --leg adjoint|batched|batched_small|si   # one leg alone, for profiling
 
 `value` is the fp64 FLOP rate the hardware counts (the paper's measure,
 Eq. 2): the fp64 VALU instructions of the tile kernel, counted once with
@@ -331,6 +331,70 @@ def batched_leg(gpp, I, stream, reps=3):
                     "generator, seed 1000+s for state s (not the seed-3 host values)"}
 
 
+def batched_small_leg(gpp, I, stream, reps=5):
+    """Many small states (256 states of 32..128 bands and 1024..4096 rows):
+    one graph-replayed gpp_sigma_batched call against 256 gpp_sigma_fwd
+    calls in a row, both straight through the C ABI with argument structs
+    built once, so that neither side pays the Python binding's per-call
+    checks.  Each small state alone leaves most of the GPU idle."""
+    import torch
+    from paper_2008_11326_amd import _lib
+    lib = _lib.load()
+    dims = I.small_batched_dims()
+    states = [I.make_problem_device(dd, 2000 + k) for k, dd in enumerate(dims)]
+    nw = dims[0].nfreq
+    dev = torch.device("cuda:0")
+    keys = ("aqsmtemp", "aqsntemp", "I_eps_array", "wtilde_array", "vcoul", "wx_array")
+    ins = (_lib.GppInputs * len(dims))()
+    for k, st in enumerate(states):
+        ins[k] = _lib.GppInputs(*[C.c_void_p(st[key].data_ptr()) for key in keys])
+    cdims = [_lib.dims_struct(*dd.as_tuple()) for dd in dims]
+    plan = gpp.Plan([dd.as_tuple() for dd in dims])
+    out = (torch.empty((len(dims), nw), dtype=torch.complex128, device=dev),
+           torch.empty((len(dims), nw), dtype=torch.complex128, device=dev))
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    seq_out = (torch.empty_like(out[0]), torch.empty_like(out[1]))
+    seq_ws = torch.empty(max(int(lib.gpp_sigma_fwd_workspace(C.byref(cd))) for cd in cdims),
+                         dtype=torch.uint8, device=dev)
+    sp = C.c_void_p(stream.cuda_stream)
+    row = 16 * nw
+
+    def batched():
+        _lib.check(lib.gpp_sigma_batched(plan._h, ins, out[0].data_ptr(), out[1].data_ptr(),
+                                         ws.data_ptr(), ws.numel(), sp), "gpp_sigma_batched")
+
+    def sequential():
+        a0, x0 = seq_out[0].data_ptr(), seq_out[1].data_ptr()
+        w0, wn = seq_ws.data_ptr(), seq_ws.numel()
+        for k, cd in enumerate(cdims):
+            st = lib.gpp_sigma_fwd(C.byref(cd), C.byref(ins[k]), a0 + k * row, x0 + k * row,
+                                   w0, wn, sp)
+            if st:
+                _lib.check(st, "gpp_sigma_fwd")
+    batched()
+    torch.cuda.synchronize()  # first call tunes (or reads the cache) and captures
+    bat = min(timed_ms(batched, stream, 1) for _ in range(reps))
+    seq = min(timed_ms(sequential, stream, 1) for _ in range(reps))
+    worst = 0.0
+    for got, ref in ((out[0], seq_out[0]), (out[1], seq_out[1])):
+        worst = max(worst, float(torch.max(torch.abs(got - ref) / torch.abs(ref))))
+    terms = sum(dd.ch_terms + dd.sx_terms for dd in dims)
+    info = plan.info()
+    plan.close()
+    return {"states": len(dims), "terms": terms, "batched_ms": round(bat, 4),
+            "sequential_plain_ms": round(seq, 4),
+            "batched_tflops": round(FLOP_PER_TERM * terms / (bat * 1e-3) / 1e12, 3),
+            "sequential_tflops": round(FLOP_PER_TERM * terms / (seq * 1e-3) / 1e12, 3),
+            "speedup_vs_sequential_plain": round(seq / bat, 3),
+            "max_rel_diff_vs_plain": worst,
+            "plan": {k: info[k] for k in ("bands_per_group", "schedule_order", "schedule",
+                                           "waves", "candidates", "from_cache")},
+            "timing": "best of 5, HIP events on the launch stream; both sides call the C ABI",
+            "data": "synthetic: 256 state sizes from default_rng(5) (32..128 bands, "
+                    "1024..4096 rows, ngpown = ncouls // 20, nvband 2, nfreq 3), values "
+                    "drawn on the device, seed 2000+s for state s"}
+
+
 def si_leg(gpp, I, stream, steps=5, warmup=2):
     """The Si-shaped per-task workload (512 bands, 32768 rows, 1638 columns)."""
     r, _, res = fwd_leg(gpp, I, "si", steps, warmup, stream)
@@ -355,7 +419,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Si-shaped, adjoint, batched and FMA-peak legs")
-    ap.add_argument("--leg", choices=("all", "adjoint", "batched", "si"), default="all",
+    ap.add_argument("--leg", choices=("all", "adjoint", "batched", "batched_small", "si"),
+                    default="all",
                     help="adjoint, batched or si: run only that leg and print its JSON "
                          "(for per-kernel profiling); all: the benchmark line")
     args = ap.parse_args()
@@ -376,7 +441,8 @@ def main():
     _lib.load()  # fail loudly if the HIP library is missing
     stream = torch.cuda.current_stream(torch.device("cuda:0"))
     if args.leg != "all":
-        leg = {"adjoint": adjoint_leg, "batched": batched_leg, "si": si_leg}[args.leg]
+        leg = {"adjoint": adjoint_leg, "batched": batched_leg,
+               "batched_small": batched_small_leg, "si": si_leg}[args.leg]
         log(f"[bench] {args.leg} leg only")
         print(json.dumps({"leg": args.leg, **leg(gpp, I, stream)}), flush=True)
         return
@@ -435,6 +501,8 @@ def main():
         out["adjoint"] = adjoint_leg(gpp, I, stream)
         log("[bench] batched leg")
         out["batched"] = batched_leg(gpp, I, stream)
+        log("[bench] batched leg, many small states")
+        out["batched_small"] = batched_small_leg(gpp, I, stream)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded slice")

@@ -45,7 +45,7 @@ import numpy as np
 __all__ = [
     "Dims", "Problem", "Workload", "WORKLOADS", "make_problem",
     "make_problem_device", "make_upstream_grad", "make_fd_entries",
-    "batched_dims", "make_batched", "workload",
+    "batched_dims", "small_batched_dims", "make_batched", "workload",
 ]
 
 
@@ -187,14 +187,29 @@ def make_fd_entries(dims: Dims, rng, count: int = 1000) -> dict:
 
 
 def batched_dims(seed: int = BATCHED_SEED, nstates: int = BATCHED_STATES,
-                 nfreq: int = 3) -> List[Dims]:
-    """Per-state sizes of the batched workload: number_bands uniform in
-    {64..512}, ncouls uniform in {4096..32768} step 256, ngpown = ncouls // 20,
-    nvband = 2."""
+                 nfreq: int = 3, bands=(64, 512), rows256=(16, 128)) -> List[Dims]:
+    """Per-state sizes of a batched workload: number_bands uniform in
+    {bands[0]..bands[1]}, ncouls = 256 * uniform{rows256[0]..rows256[1]},
+    ngpown = ncouls // 20, nvband = 2.  The defaults are the 64-state
+    workload: 64..512 bands, 4096..32768 rows."""
     rng = np.random.default_rng(seed)
-    nb = rng.integers(64, 513, nstates)
-    ng = 256 * rng.integers(16, 129, nstates)
+    nb = rng.integers(bands[0], bands[1] + 1, nstates)
+    ng = 256 * rng.integers(rows256[0], rows256[1] + 1, nstates)
     return [Dims(int(b), 2, int(g), int(g) // 20, nfreq) for b, g in zip(nb, ng)]
+
+
+# Many small states (a small system's quasiparticle states): 256 states of
+# 32..128 bands and 1024..4096 rows, sizes from default_rng(5).  Each one
+# alone fills a fraction of the GPU for tens of microseconds.
+SMALL_BATCHED_SEED = 5
+SMALL_BATCHED_STATES = 256
+SMALL_BATCHED_BANDS = (32, 128)
+SMALL_BATCHED_ROWS256 = (4, 16)
+
+
+def small_batched_dims(nfreq: int = 3) -> List[Dims]:
+    return batched_dims(SMALL_BATCHED_SEED, SMALL_BATCHED_STATES, nfreq,
+                        SMALL_BATCHED_BANDS, SMALL_BATCHED_ROWS256)
 
 
 def make_batched(seed: int = BATCHED_SEED, nstates: int = BATCHED_STATES,

@@ -209,6 +209,7 @@ batched_queue(const StateDesc *__restrict__ st, long nchunks, int chunk_tiles,
 // forward's registers and two-column tiles.
 template <int NW, int BU>
 __global__ void __launch_bounds__(kBatThreads)
+__attribute__((amdgpu_waves_per_eu(fwd_min_waves(NW))))
 batched_flat(const StateDesc *__restrict__ st, int nstates, double *__restrict__ partials)
 {
     __shared__ double red[kBatWaves][4 * NW];
@@ -355,17 +356,12 @@ batched_reduce(const double *__restrict__ partials, int nwaves, double2 *__restr
     }
 }
 
-// The kernel of a tile variant, or nullptr where its batch inversion would
-// hold more than 12 denominators (columns x bands x frequencies), which the
-// plan never asks for.
+// The kernel of a persistent tile variant, or nullptr where its batch
+// inversion would hold more than 12 denominators (columns x bands x
+// frequencies), which the plan never asks for.
 template <int NW, int BU>
 static const void *persistent_ptr(int sched)
 {
-    if (sched == kSchedFlat) {
-        if constexpr (fwd_cols(NW) * BU * NW <= 12)
-            return reinterpret_cast<const void *>(&batched_flat<NW, BU>);
-        return nullptr;
-    }
     if constexpr (bat_cols(NW) * BU * NW <= 12)
         return (sched == kSchedQueue || sched == kSchedXcdQueues)
                    ? reinterpret_cast<const void *>(&batched_queue<NW, BU>)
@@ -375,11 +371,16 @@ static const void *persistent_ptr(int sched)
 
 const void *batched_kernel(int nw, int bu, int sched)
 {
-#define GPP_K(NWV)                                               \
-    case NWV:                                                    \
-        if (bu == 1) return persistent_ptr<NWV, 1>(sched);       \
-        if (bu == 2) return persistent_ptr<NWV, 2>(sched);       \
-        if (bu == 3) return persistent_ptr<NWV, 3>(sched);       \
+#define GPP_K(NWV)                                                                 \
+    case NWV:                                                                      \
+        if (sched == kSchedFlat) /* the plain forward's tile shape only */         \
+            return bu == fwd_bands(NWV)                                            \
+                       ? reinterpret_cast<const void *>(                           \
+                             &batched_flat<NWV, fwd_bands(NWV)>)                   \
+                       : nullptr;                                                  \
+        if (bu == 1) return persistent_ptr<NWV, 1>(sched);                         \
+        if (bu == 2) return persistent_ptr<NWV, 2>(sched);                         \
+        if (bu == 3) return persistent_ptr<NWV, 3>(sched);                         \
         return nullptr;
     switch (nw) {
         GPP_K(1) GPP_K(2) GPP_K(3) GPP_K(4) GPP_K(5) GPP_K(6) GPP_K(7) GPP_K(8)

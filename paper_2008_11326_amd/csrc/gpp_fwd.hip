@@ -37,25 +37,21 @@ namespace gpp {
 
 constexpr int kFwdWaves = 4;
 constexpr int kFwdThreads = kFwdWaves * kWave;
-// G' columns per wave tile and bands per batch-inverted group (K = bands *
-// nfreq reciprocals from one hardware reciprocal) for nfreq <= 3 come from
-// fwd_cols and fwd_bands (gpp_internal.h), and an optional cap on VGPRs
-// through a minimum number of waves per SIMD; chosen by measurement on
-// MI355X.  Two columns per wave let each aqsntemp load
-// serve both: 153 VGPRs (3 waves per SIMD) at nfreq 3 with 2-band groups,
-// 2.8-3.1 % faster than one column with 3-band groups (105 VGPRs, 4 waves).
-// Three columns need about 200 VGPRs (2 waves) and measured 3-30 % slower.
-// With 4 or more frequencies a second column would leave 2 waves or fewer,
-// so those keep one column.
-#ifndef GPP_FWD_MIN_WAVES
-#define GPP_FWD_MIN_WAVES 1
-#endif
+// G' columns per wave tile and bands per batch-inverted group (K = columns
+// x bands x nfreq reciprocals from one hardware reciprocal) come from
+// fwd_cols and fwd_bands, and a cap on VGPRs through a minimum number of
+// waves per SIMD from fwd_min_waves (gpp_internal.h), all chosen by
+// measurement on MI355X.  At nfreq 3, two columns per wave let each
+// aqsntemp load serve both: 153 VGPRs (3 waves per SIMD) with 2-band
+// groups, 2.8-3.1 % faster than one column with 3-band groups (105 VGPRs,
+// 4 waves); three columns need about 200 VGPRs (2 waves) and measured
+// 3-30 % slower.
 constexpr int kRedThreads = 256;
 constexpr long kRedBlocks = 512;  // first reduction stage
 
 template <int NW, int BU>
 __global__ void __launch_bounds__(kFwdThreads)
-__attribute__((amdgpu_waves_per_eu(GPP_FWD_MIN_WAVES)))
+__attribute__((amdgpu_waves_per_eu(fwd_min_waves(NW))))
 fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
           const double2 *__restrict__ aqsm, const double2 *__restrict__ aqsn,
           const double2 *__restrict__ ieps, const double2 *__restrict__ wt,

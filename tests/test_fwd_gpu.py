@@ -71,6 +71,9 @@ def _tile_edge_problem(seed, nb, nv, ng, npw, nw, poles=0.0):
     (7, 7, 200, 9, 3), (1, 1, 130, 1, 3), (1, 0, 1, 1, 3), (40, 3, 777, 13, 3),
     (3, 1, 129, 5, 1), (3, 1, 129, 5, 2), (3, 1, 129, 5, 4), (3, 1, 129, 5, 5),
     (3, 1, 129, 5, 6), (3, 1, 129, 5, 7), (3, 1, 129, 5, 8),
+    # several band groups and a ragged band tail, ragged column tiles
+    (9, 2, 200, 7, 1), (9, 2, 200, 7, 2), (9, 2, 200, 7, 4), (9, 2, 200, 7, 5),
+    (9, 2, 200, 7, 6), (9, 2, 200, 7, 7), (10, 2, 200, 8, 8),
     # several blocks of the tile walk (64 column tiles each) with a short last one
     (6, 1, 321, 300, 3), (4, 1, 321, 150, 5),
 ])

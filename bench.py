@@ -38,7 +38,7 @@ if ROOT not in sys.path:
 METRIC = "GPP FP64 TFLOP/s and % FP64 peak; batched/adjoint vs plain at 1e-12 rel"
 FLOP_PER_TERM = 21
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 fp64 FLOP/clk/CU
-FWD_SOURCES = ("gpp_fwd.hip", "gpp_fwd_tile.h", "gpp_device.h", "gpp_internal.h")
+FWD_SOURCES = ("gpp_fwd.hip", "gpp_fwd_tile.h", "gpp_device.h", "gpp_fwd_shape.h")
 
 
 def log(msg):

@@ -25,7 +25,7 @@ LIB = os.path.join(PKG, "libgpp.so")
 SOURCES = ["gpp_api.hip", "gpp_fwd.hip", "gpp_bwd.hip", "gpp_batched.hip", "gpp_plan.hip",
            "gpp_ladder.hip", "gpp_noalloc.hip",
            "gpp_microbench.hip"]
-HEADERS = ["gpp_device.h", "gpp_fwd_tile.h", "gpp_internal.h"]
+HEADERS = ["gpp_device.h", "gpp_fwd_tile.h", "gpp_fwd_shape.h", "gpp_internal.h"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

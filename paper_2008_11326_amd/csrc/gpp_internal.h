@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "gpp.h"
+#include "gpp_fwd_shape.h"
 
 namespace gpp {
 
@@ -92,47 +93,6 @@ const void *batched_kernel(int nw, int bu, int sched);
 hipError_t launch_batched(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st);
 constexpr int kXcdCount = 8;
 
-// Tile shape of the plain forward for nfreq frequencies (shared by the
-// plain and batched-flat forwards and the plan's tile counts): G' columns
-// per wave tile, and bands per batch-inverted group, so that a group holds
-// columns x bands x nfreq <= 12 denominators.  More columns let each
-// aqsntemp load serve more terms; the accumulators (columns x nfreq x 4
-// doubles) bound how many fit.  Pairs (columns, bands) for nfreq = 1..8;
-// nfreq 3 takes GPP_FWD_COLS x GPP_FWD_BANDS.  Measured on MI355X at 512
-// bands, 32768 rows, 1638 columns (best of 3 alternating rounds): nfreq 2
-// with three columns 2 % faster than with two; nfreq 5 and 6 with 2-band
-// groups 20 % and 15 % faster than 1-band ones; nfreq 1 with 2 x 2 faster
-// than 2 x 6, 3 x 4, 4 x 3 or 6 x 2; nfreq 4 with 1 x 2 faster than 1 x 3
-// or 2 x 1.
-#ifndef GPP_FWD_COLS
-#define GPP_FWD_COLS 2
-#endif
-#ifndef GPP_FWD_BANDS
-#define GPP_FWD_BANDS 2
-#endif
-#ifndef GPP_FWD_SHAPE
-#define GPP_FWD_SHAPE 2, 2, 3, 2, GPP_FWD_COLS, GPP_FWD_BANDS, 1, 2, 1, 2, 1, 2, 1, 1, 1, 1
-#endif
-constexpr int kFwdShape[16] = {GPP_FWD_SHAPE};
-constexpr int fwd_cols(int nw) { return kFwdShape[2 * (nw - 1)]; }
-constexpr int fwd_bands(int nw) { return kFwdShape[2 * (nw - 1) + 1]; }
-constexpr bool fwd_shapes_fit()
-{
-    for (int nw = 1; nw <= 8; ++nw)
-        if (fwd_cols(nw) < 1 || fwd_bands(nw) < 1 || fwd_cols(nw) * fwd_bands(nw) * nw > 12)
-            return false;
-    return true;
-}
-static_assert(fwd_shapes_fit(), "a forward tile's batch inversion holds at most 12 denominators");
-// Minimum waves per SIMD (a VGPR cap) of the forward tile kernels for
-// nfreq = 1..8.  With 7 or 8 frequencies the one-column tile takes 170 and
-// 188 VGPRs, i.e. 2 waves; capped at 168 (3 waves; 2 and 34 bytes of
-// spills) it ran 24 % and 20 % faster.
-#ifndef GPP_FWD_MIN_WAVES
-#define GPP_FWD_MIN_WAVES 1, 1, 1, 1, 1, 1, 3, 3
-#endif
-constexpr int kFwdMinWaves[8] = {GPP_FWD_MIN_WAVES};
-constexpr int fwd_min_waves(int nw) { return kFwdMinWaves[nw - 1]; }
 // The same for the batched persistent forward's tiles, and the register cap
 // (minimum waves per SIMD) of its two-column form.  The batched kernel keeps
 // one column: with two, its persistent loop runs out of scalar registers,

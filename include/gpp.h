@@ -123,15 +123,15 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in,
  * so make one call before capturing a graph.
  *   dims, in, achtemp, asxtemp, stream: as gpp_sigma_fwd
  * Sizes whose gpp_sigma_fwd_workspace(dims) exceeds GPP_NOALLOC_SCRATCH_BYTES
- * return GPP_ERR_WORKSPACE and enqueue nothing (48 MiB covers 1024 bands x
- * 65536 rows x 3276 columns at nfreq 3).  Every call on one device shares
+ * return GPP_ERR_WORKSPACE and enqueue nothing (96 MiB covers 1024 bands x
+ * 65536 rows x 3276 columns at nfreq 3: 80.6 MB).  Every call on one device shares
  * that device's array: calls that overlap in time on one device (different
  * streams, or host threads without ordering) race and give wrong results;
  * calls ordered on one stream are safe.  Nothing in the array needs to
  * start at zero (every partial row a kernel reads was written earlier in
  * the same call).
  */
-#define GPP_NOALLOC_SCRATCH_BYTES (48u << 20)
+#define GPP_NOALLOC_SCRATCH_BYTES (96u << 20)
 gpp_status gpp_sigma_fwd_noalloc(const gpp_dims *dims, const gpp_inputs *in, double *achtemp,
                                  double *asxtemp, void *stream);
 

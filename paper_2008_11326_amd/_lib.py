@@ -18,7 +18,7 @@ GPP_OK = 0
 STATUS = {0: "GPP_OK", 1: "GPP_ERR_INVALID", 2: "GPP_ERR_HIP",
           3: "GPP_ERR_NOMEM", 4: "GPP_ERR_WORKSPACE", 5: "GPP_ERR_UNSUPPORTED"}
 MAX_NFREQ = 8
-NOALLOC_SCRATCH_BYTES = 48 << 20  # GPP_NOALLOC_SCRATCH_BYTES of include/gpp.h
+NOALLOC_SCRATCH_BYTES = 96 << 20  # GPP_NOALLOC_SCRATCH_BYTES of include/gpp.h
 
 
 class GppError(RuntimeError):

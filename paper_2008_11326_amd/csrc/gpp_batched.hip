@@ -63,11 +63,11 @@ __device__ __forceinline__ void state_tile(const StateDesc &d, long local, int l
     const int gt = (int)(local / npt);
     const int pt = (int)(local - (long)gt * npt);
     if (C == 1) {
-        fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, pt, gt, lane, as_global(d.aqsm),
+        fwd_tile_body<NW, BU>(d.nb, d.nv, 0, d.nb, d.ng, pt, gt, lane, as_global(d.aqsm),
                               as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
                               as_global(d.vcoul), as_global(d.wx), a, x);
     } else {
-        fwd_tile_body_cols<NW, BU, C>(d.nb, d.nv, d.ng, d.np, C * pt, gt, lane,
+        fwd_tile_body_cols<NW, BU, C>(d.nb, d.nv, 0, d.nb, d.ng, d.np, C * pt, gt, lane,
                                       as_global(d.aqsm), as_global(d.aqsn), as_global(d.ieps),
                                       as_global(d.wt), as_global(d.vcoul), as_global(d.wx), a,
                                       x);
@@ -247,14 +247,14 @@ batched_flat(const StateDesc *__restrict__ st, int nstates, double *__restrict__
 #pragma unroll
     for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
     if (local < ntile) {
-        int gt, pt;
-        tile_coords(local, npt, (d.ng + kWave - 1) / kWave, gt, pt);
+        int gt, pt, ck;
+        tile_coords(local, npt, (d.ng + kWave - 1) / kWave, 1, gt, pt, ck);
         if (C == 1) {
-            fwd_tile_body<NW, BU>(d.nb, d.nv, d.ng, pt, gt, lane, as_global(d.aqsm),
+            fwd_tile_body<NW, BU>(d.nb, d.nv, 0, d.nb, d.ng, pt, gt, lane, as_global(d.aqsm),
                                   as_global(d.aqsn), as_global(d.ieps), as_global(d.wt),
                                   as_global(d.vcoul), as_global(d.wx), ach, asx);
         } else {
-            fwd_tile_body_cols<NW, BU, C>(d.nb, d.nv, d.ng, d.np, C * pt, gt, lane,
+            fwd_tile_body_cols<NW, BU, C>(d.nb, d.nv, 0, d.nb, d.ng, d.np, C * pt, gt, lane,
                                           as_global(d.aqsm), as_global(d.aqsn),
                                           as_global(d.ieps), as_global(d.wt),
                                           as_global(d.vcoul), as_global(d.wx), ach, asx);

@@ -52,7 +52,7 @@ constexpr long kRedBlocks = 512;  // first reduction stage
 template <int NW, int BU>
 __global__ void __launch_bounds__(kFwdThreads)
 __attribute__((amdgpu_waves_per_eu(fwd_min_waves(NW))))
-fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
+fwd_tiles(int nb, int nv, int ng, int np, long ntiles, int nchunk, int chunk_bands,
           const double2 *__restrict__ aqsm, const double2 *__restrict__ aqsn,
           const double2 *__restrict__ ieps, const double2 *__restrict__ wt,
           const double *__restrict__ vcoul, const double *__restrict__ wx,
@@ -71,16 +71,19 @@ fwd_tiles(int nb, int nv, int ng, int np, long ntiles,
         // consecutive tiles share a g-tile (and so the same aqsntemp rows)
         constexpr int C = fwd_cols(NW);
         const int npt = (np + C - 1) / C;  // column tiles per g-tile
-        int gt, pt;
-        tile_coords(tile, npt, (ng + kWave - 1) / kWave, gt, pt);
+        int gt, pt, ck;
+        tile_coords(tile, npt, (ng + kWave - 1) / kWave, nchunk, gt, pt, ck);
+        const int n_lo = ck * chunk_bands;
+        const int n_hi = nb - n_lo < chunk_bands ? nb : n_lo + chunk_bands;
         if (C == 1) {
-            fwd_tile_body<NW, BU>(nb, nv, ng, pt, gt, lane, as_global(aqsm), as_global(aqsn),
-                                  as_global(ieps), as_global(wt), as_global(vcoul),
-                                  as_global(wx), ach, asx);
+            fwd_tile_body<NW, BU>(nb, nv, n_lo, n_hi, ng, pt, gt, lane, as_global(aqsm),
+                                  as_global(aqsn), as_global(ieps), as_global(wt),
+                                  as_global(vcoul), as_global(wx), ach, asx);
         } else {
-            fwd_tile_body_cols<NW, BU, C>(nb, nv, ng, np, C * pt, gt, lane, as_global(aqsm),
-                                          as_global(aqsn), as_global(ieps), as_global(wt),
-                                          as_global(vcoul), as_global(wx), ach, asx);
+            fwd_tile_body_cols<NW, BU, C>(nb, nv, n_lo, n_hi, ng, np, C * pt, gt, lane,
+                                          as_global(aqsm), as_global(aqsn), as_global(ieps),
+                                          as_global(wt), as_global(vcoul), as_global(wx), ach,
+                                          asx);
         }
     }
 
@@ -222,7 +225,8 @@ FwdGeometry fwd_geometry(const Dims32 &d)
     if (d.nb == 0 || d.ng == 0 || d.np == 0) return geo;
     const long gtiles = (d.ng + kWave - 1) / kWave;
     const int cols = fwd_cols(d.nw);
-    geo.ntiles = gtiles * ((d.np + cols - 1) / cols);
+    fwd_band_chunks(d.nb, d.nw, geo.nchunk, geo.chunk_bands);
+    geo.ntiles = gtiles * ((d.np + cols - 1) / cols) * geo.nchunk;
     geo.nblocks = (geo.ntiles + kFwdWaves - 1) / kFwdWaves;
     geo.red_blocks = geo.nblocks < kRedBlocks ? geo.nblocks : kRedBlocks;
     geo.red_chunk = (geo.nblocks + geo.red_blocks - 1) / geo.red_blocks;
@@ -242,8 +246,9 @@ static hipError_t launch_fwd_nw(const Dims32 &d, const FwdGeometry &geo, const D
     double *stage = ws + (size_t)geo.nblocks * 4 * NW;
     constexpr int BU = fwd_bands(NW);
     hipLaunchKernelGGL((fwd_tiles<NW, BU>), dim3((unsigned)geo.nblocks),
-                       dim3(kFwdThreads), 0, st, d.nb, d.nv, d.ng, d.np, geo.ntiles, in.aqsm,
-                       in.aqsn, in.ieps, in.wt, in.vcoul, in.wx, partials);
+                       dim3(kFwdThreads), 0, st, d.nb, d.nv, d.ng, d.np, geo.ntiles, geo.nchunk,
+                       geo.chunk_bands, in.aqsm, in.aqsn, in.ieps, in.wt, in.vcoul, in.wx,
+                       partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_rows<NW>, dim3((unsigned)geo.red_blocks), dim3(kRedThreads), 0,

@@ -45,4 +45,29 @@ static_assert(fwd_shapes_fit(), "a forward tile's batch inversion holds at most 
 constexpr int kFwdMinWaves[8] = {GPP_FWD_MIN_WAVES};
 constexpr int fwd_min_waves(int nw) { return kFwdMinWaves[nw - 1]; }
 
+// Band chunks of the plain forward's tiles.  The waves an XCD holds at
+// once start and end together, so a value one tile reads comes back to the
+// next tiles only after a whole tile's band loop of other traffic (about
+// 8 KB per band for the resident tiles of one XCD); splitting the band
+// loop into chunks of at most GPP_FWD_CHUNK_BANDS bands keeps that inside
+// the XCD's 4 MB L2.  Every chunk of a tile adds its own partial sums (the
+// sums are linear in the bands), so chunks cost their own set-up, exchange
+// sums and partial row.  0 turns chunking off.  Chunks hold whole band
+// groups except the last.
+#ifndef GPP_FWD_CHUNK_BANDS
+#define GPP_FWD_CHUNK_BANDS 512
+#endif
+inline void fwd_band_chunks(int nb, int nw, int &nchunk, int &chunk_bands)
+{
+    nchunk = 1;
+    chunk_bands = nb;
+    if (GPP_FWD_CHUNK_BANDS <= 0 || nb <= GPP_FWD_CHUNK_BANDS) return;
+    const int bu = fwd_bands(nw);
+    const int want = (nb + GPP_FWD_CHUNK_BANDS - 1) / GPP_FWD_CHUNK_BANDS;
+    int cb = (nb + want - 1) / want;
+    cb = (cb + bu - 1) / bu * bu;
+    chunk_bands = cb;
+    nchunk = (nb + cb - 1) / cb;
+}
+
 }  // namespace gpp

@@ -24,28 +24,37 @@ namespace gpp {
 #define GPP_FWD_COL_BLOCK 64
 #endif
 
-// (g-tile, column tile) of a tile index, a bijection on [0, gtiles * npt).
-// The tile is wave-uniform; the results are made scalar explicitly, since
-// the divisions run on the vector unit and a column index left in vector
-// registers would turn the tile's aqsmtemp loads into vector loads.
-__device__ inline void tile_coords(long tile, int npt, int gtiles, int &gt, int &pt)
+// (g-tile, column tile, band chunk) of a tile index, a bijection on
+// [0, gtiles * npt * nchunk).  Within a block of Q column tiles the walk
+// takes band chunk by band chunk, each through all g-tiles.  The results
+// are wave-uniform and made scalar explicitly, since the divisions run on
+// the vector unit and a column index left in vector registers would turn
+// the tile's aqsmtemp loads into vector loads.
+__device__ inline void tile_coords(long tile, int npt, int gtiles, int nchunk, int &gt, int &pt,
+                                   int &ck)
 {
 #if GPP_FWD_COL_BLOCK > 0
     constexpr int Q = GPP_FWD_COL_BLOCK;
-    const long per = (long)Q * gtiles;
+    const long per = (long)Q * gtiles * nchunk;
     const int c = (int)(tile / per);
-    const long r = tile - (long)c * per;
+    long r = tile - (long)c * per;
     const int c0 = c * Q;
     const int qc = npt - c0 < Q ? npt - c0 : Q;  // the last block may be short
+    const long per_chunk = (long)qc * gtiles;
+    ck = (int)(r / per_chunk);
+    r -= (long)ck * per_chunk;
     gt = (int)(r / qc);
     pt = c0 + (int)(r - (long)gt * qc);
 #else
-    (void)gtiles;
-    gt = (int)(tile / npt);
-    pt = (int)(tile - (long)gt * npt);
+    const long per_chunk = (long)gtiles * npt;
+    ck = (int)(tile / per_chunk);
+    const long r = tile - (long)ck * per_chunk;
+    gt = (int)(r / npt);
+    pt = (int)(r - (long)gt * npt);
 #endif
     gt = __builtin_amdgcn_readfirstlane(gt);
     pt = __builtin_amdgcn_readfirstlane(pt);
+    ck = __builtin_amdgcn_readfirstlane(ck);
 }
 
 // CH-only accumulation for BU consecutive unoccupied bands starting at n.
@@ -213,17 +222,19 @@ __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aq
     ch_group_an<NW, BU>(n, nb, ng, an, am_col, wx, a, wi2, thr, wide, P1, P2);
 }
 
-// Occupied bands n < nv of one lane and one column: Coulomb-hole terms into
-// P1/P2 and screened-exchange terms (ssx / e) into SX, with full complex
-// arithmetic and one reciprocal per term.
+// Occupied bands n0 <= n < n1 (all below nvband) of one lane and one
+// column: Coulomb-hole terms into P1/P2 and screened-exchange terms
+// (ssx / e) into SX, with full complex arithmetic and one reciprocal per
+// term.
 template <int NW>
-__device__ __forceinline__ void occupied_bands(int nv, int nb, int ng, gptr<double2> an_col,
-                                               gptr<double2> am_col, gptr<double> wx, cplx om,
-                                               double wi2, double wtr, double thr,
-                                               cplx (&P1)[NW], cplx (&P2)[NW], cplx (&SX)[NW])
+__device__ __forceinline__ void occupied_bands(int n0, int n1, int nb, int ng,
+                                               gptr<double2> an_col, gptr<double2> am_col,
+                                               gptr<double> wx, cplx om, double wi2, double wtr,
+                                               double thr, cplx (&P1)[NW], cplx (&P2)[NW],
+                                               cplx (&SX)[NW])
 {
     const double a = om.re, b = om.im;
-    for (int n = 0; n < nv; ++n) {
+    for (int n = n0; n < n1; ++n) {
         const cplx an = cload(an_col + (size_t)n * ng);
         const cplx am = cload(am_col + (size_t)n * ng);
         const cplx qm = cmul_conj(an, am);
@@ -253,12 +264,14 @@ __device__ __forceinline__ void occupied_bands(int nv, int nb, int ng, gptr<doub
     }
 }
 
-// One tile: lane g = gt*64 + lane of column p.  On return ach[w] holds this
-// lane's Coulomb-hole contribution (still to be summed over the wave) and
-// asx[w] the wave's screened-exchange total (wave-uniform).  Must be called
-// by all 64 lanes of a wave together (wave reductions inside).
+// One tile: lane g = gt*64 + lane of column p, bands n_lo <= n < n_hi.  On
+// return ach[w] holds this lane's Coulomb-hole contribution (still to be
+// summed over the wave) and asx[w] the wave's screened-exchange total
+// (wave-uniform).  Must be called by all 64 lanes of a wave together (wave
+// reductions inside).
 template <int NW, int BU>
-__device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int gt, int lane,
+__device__ __forceinline__ void fwd_tile_body(int nb, int nv, int n_lo, int n_hi, int ng, int p,
+                                              int gt, int lane,
                                               gptr<double2> aqsm, gptr<double2> aqsn,
                                               gptr<double2> ieps, gptr<double2> wt,
                                               gptr<double> vcoul, gptr<double> wx,
@@ -286,10 +299,11 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
     const cplx ev = cscale(v, e);
 
     // occupied bands: screened exchange (SX) and Coulomb hole (CH)
-    occupied_bands<NW>(nv, nb, ng, an_col, am_col, wx, om, wi2, wtr, thr, P1, P2, SX);
+    const int occ_hi = nv < n_hi ? nv : n_hi;
+    occupied_bands<NW>(n_lo, occ_hi, nb, ng, an_col, am_col, wx, om, wi2, wtr, thr, P1, P2, SX);
     // The exchange sums are finished here and reduced over the wave into
     // scalar registers, so they hold no vector registers in the hot loop.
-    if (nv > 0) {
+    if (occ_hi > n_lo) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const cplx t = cmul(ev, SX[w]);
@@ -302,10 +316,10 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
 
     // unoccupied bands: CH only -- the hot loop
     const bool wide = wi2 >= kMinUnclampedWi2;
-    int n = nv;
-    for (; n + BU <= nb; n += BU)
+    int n = nv > n_lo ? nv : n_lo;
+    for (; n + BU <= n_hi; n += BU)
         ch_group<NW, BU>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
-    for (; n < nb; ++n)
+    for (; n < n_hi; ++n)
         ch_group<NW, 1>(n, nb, ng, aqsn, goff, am_col, wx, a, wi2, thr, wide, P1, P2);
 
 #pragma unroll
@@ -318,14 +332,15 @@ __device__ __forceinline__ void fwd_tile_body(int nb, int nv, int ng, int p, int
     }
 }
 
-// NC consecutive G' columns p0 .. p0+NC-1 of one 64-row tile per wave:
-// each aqsntemp element a lane loads serves all of them, which divides the
-// vector-memory traffic of the hot loop by NC.  Columns at or beyond np
-// repeat p0 and their contribution is dropped.  Outputs as fwd_tile_body,
-// for the NC columns together.
+// NC consecutive G' columns p0 .. p0+NC-1 of one 64-row tile per wave,
+// bands n_lo <= n < n_hi: each aqsntemp element a lane loads serves all of
+// them, which divides the vector-memory traffic of the hot loop by NC.
+// Columns at or beyond np repeat p0 and their contribution is dropped.
+// Outputs as fwd_tile_body, for the NC columns together.
 template <int NW, int BU, int NC>
-__device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int np, int p0,
-                                                   int gt, int lane, gptr<double2> aqsm,
+__device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int n_lo, int n_hi, int ng,
+                                                   int np, int p0, int gt, int lane,
+                                                   gptr<double2> aqsm,
                                                    gptr<double2> aqsn, gptr<double2> ieps,
                                                    gptr<double2> wt, gptr<double> vcoul,
                                                    gptr<double> wx, cplx (&ach)[NW],
@@ -359,7 +374,8 @@ __device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int n
 
     // occupied bands, column by column; the exchange sums of all columns
     // are reduced over the wave into scalar registers before the hot loop
-    if (nv > 0) {
+    const int occ_hi = nv < n_hi ? nv : n_hi;
+    if (occ_hi > n_lo) {
         cplx sx[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) sx[w] = cmake(0.0, 0.0);
@@ -368,7 +384,7 @@ __device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int n
             cplx SX[NW];
 #pragma unroll
             for (int w = 0; w < NW; ++w) SX[w] = cmake(0.0, 0.0);
-            occupied_bands<NW>(nv, nb, ng, an_col, aqsm + pc[c], wx, om[c], wi2[c],
+            occupied_bands<NW>(n_lo, occ_hi, nb, ng, an_col, aqsm + pc[c], wx, om[c], wi2[c],
                                fma(a[c], a[c], wi2[c]), thr[c], P1[c], P2[c], SX);
             const double vc = has[c] ? v : 0.0;
             const cplx ev = cscale(vc, cload(ieps + (size_t)pc[c] * ng + gc));
@@ -384,23 +400,23 @@ __device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int n
     }
 
     // unoccupied bands: CH only
-    int n = nv;
+    int n = nv > n_lo ? nv : n_lo;
 #if GPP_FWD_JOINT_INV
     bool wide_all = true;
 #pragma unroll
     for (int c = 0; c < NC; ++c) wide_all = wide_all && wide[c];
-    for (; n + BU <= nb; n += BU) {
+    for (; n + BU <= n_hi; n += BU) {
         cplx an[BU];
         load_an<BU>(n, ng, aqsn, goff, an);
         ch_group_cols<NW, BU, NC>(n, nb, ng, an, aqsm, pc, wx, a, wi2, thr, wide_all, P1, P2);
     }
-    for (; n < nb; ++n) {
+    for (; n < n_hi; ++n) {
         cplx an[1];
         load_an<1>(n, ng, aqsn, goff, an);
         ch_group_cols<NW, 1, NC>(n, nb, ng, an, aqsm, pc, wx, a, wi2, thr, wide_all, P1, P2);
     }
 #else
-    for (; n + BU <= nb; n += BU) {
+    for (; n + BU <= n_hi; n += BU) {
         cplx an[BU];
         load_an<BU>(n, ng, aqsn, goff, an);
 #pragma unroll
@@ -411,7 +427,7 @@ __device__ __forceinline__ void fwd_tile_body_cols(int nb, int nv, int ng, int n
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    for (; n < nb; ++n) {
+    for (; n < n_hi; ++n) {
         cplx an[1];
         load_an<1>(n, ng, aqsn, goff, an);
 #pragma unroll

@@ -21,7 +21,9 @@ struct DevInputs {
 };
 
 struct FwdGeometry {
-    long ntiles = 0;      // (ceil(ng/64) g-tiles) x (np columns), one per wave
+    long ntiles = 0;      // g-tiles x column tiles x band chunks, one per wave
+    int nchunk = 1;       // band chunks (fwd_band_chunks)
+    int chunk_bands = 0;  // bands per chunk (the last may be shorter)
     long nblocks = 0;     // tile-kernel workgroups of 4 waves (one partial each)
     long red_blocks = 0;  // first reduction stage workgroups
     long red_chunk = 0;   // partial rows per first-stage workgroup

@@ -119,6 +119,30 @@ def test_workspace_size_is_host_only_and_monotone(lib):
     assert lib.gpp_sigma_fwd_workspace(None) == 0
 
 
+def _fwd_workgroups(lib, nb, ng, npw, nw):
+    """Workgroups of the forward's tile kernel, from its workspace size: one
+    partial row of 4 * nw doubles per workgroup, plus as many first-stage
+    rows while there are at most 512 workgroups."""
+    ws = lib.gpp_sigma_fwd_workspace(C.byref(_dims(nb, 1, ng, npw, nw)))
+    row = 32 * nw
+    assert ws % (2 * row) == 0
+    assert ws // (2 * row) <= 512
+    return ws // (2 * row)
+
+
+def test_forward_band_chunks(lib):
+    """Above 512 bands the forward splits the band loop into chunks of at
+    most 512 bands (whole band groups but the last), each tile chunk a
+    workgroup row of its own: the tile count, and so the partial rows,
+    scale with the chunk count.  64 rows x 40 columns at nfreq 3 are 20
+    two-column tiles, i.e. 5 workgroups per chunk."""
+    for nb, chunks in ((512, 1), (513, 2), (1024, 2), (1025, 3), (1536, 3), (1537, 4)):
+        assert _fwd_workgroups(lib, nb, 64, 40, 3) == 5 * chunks, nb
+    # nfreq 2 takes three columns per tile: 14 tiles per chunk, 3 chunks of
+    # at most 512 bands, four tiles per workgroup
+    assert _fwd_workgroups(lib, 1030, 64, 40, 2) == (14 * 3 + 3) // 4
+
+
 def test_python_binding_rejects_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))

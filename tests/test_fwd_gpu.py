@@ -76,6 +76,10 @@ def _tile_edge_problem(seed, nb, nv, ng, npw, nw, poles=0.0):
     (9, 2, 200, 7, 6), (9, 2, 200, 7, 7), (10, 2, 200, 8, 8),
     # several blocks of the tile walk (64 column tiles each) with a short last one
     (6, 1, 321, 300, 3), (4, 1, 321, 150, 5),
+    # more than 512 bands: the band loop splits into chunks (a ragged last
+    # one; occupied bands spanning a chunk boundary; three chunks)
+    (600, 2, 130, 9, 3), (701, 400, 70, 5, 3), (600, 3, 70, 5, 5), (1030, 1, 64, 3, 2),
+    (513, 513, 65, 3, 1),
 ])
 def test_ragged_and_nfreq(gpp, shape):
     prob = _tile_edge_problem(sum(shape), *shape)

@@ -62,6 +62,25 @@ gpp_status check_dims(const gpp_dims *d, gpp::Dims32 *out)
     return GPP_OK;
 }
 
+// The forward's tile grid (one workgroup per four tile chunks of at most
+// 512 bands) and the adjoint's two grids must each index a 32-bit launch.
+gpp_status check_fwd_grid(const gpp::Dims32 &d, const char *who)
+{
+    if (gpp::fwd_geometry(d).nblocks > kMax32)
+        return fail(GPP_ERR_INVALID, "%s: number_bands x ncouls x ngpown too large for one launch",
+                    who);
+    return GPP_OK;
+}
+
+gpp_status check_bwd_grid(const gpp::Dims32 &d, const char *who)
+{
+    const gpp::BwdGeometry g = gpp::bwd_geometry(d);
+    if (g.pair_blocks > kMax32 || g.band_blocks > kMax32)
+        return fail(GPP_ERR_INVALID, "%s: number_bands x ncouls x ngpown too large for one launch",
+                    who);
+    return GPP_OK;
+}
+
 bool misaligned(const void *p, size_t a) { return ((uintptr_t)p) % a != 0; }
 
 gpp_status check_array(const char *name, const void *p, int64_t elems, size_t align)
@@ -139,7 +158,8 @@ extern "C" {
 size_t gpp_sigma_fwd_workspace(const gpp_dims *dims)
 {
     gpp::Dims32 d;
-    if (check_dims(dims, &d) != GPP_OK) return 0;
+    if (check_dims(dims, &d) != GPP_OK || check_fwd_grid(d, "gpp_sigma_fwd_workspace") != GPP_OK)
+        return 0;
     size_t b = gpp::fwd_geometry(d).workspace_bytes;
     return b ? b : 256;
 }
@@ -153,6 +173,7 @@ gpp_status gpp_sigma_fwd(const gpp_dims *dims, const gpp_inputs *in, double *ach
     gpp::DevInputs din;
     gpp_status s;
     if ((s = check_dims(dims, &d))) return s;
+    if ((s = check_fwd_grid(d, "gpp_sigma_fwd"))) return s;
     if ((s = check_inputs(d, in, &din))) return s;
     if ((s = check_array("achtemp", achtemp, d.nw, 16)) ||
         (s = check_array("asxtemp", asxtemp, d.nw, 16)))
@@ -188,6 +209,7 @@ gpp_status gpp_sigma_qp(const gpp_dims *dims, const gpp_inputs *in, double freq_
     if (!(energy == energy) || !(vxc == vxc) || !(energy - energy == 0.0) ||
         !(vxc - vxc == 0.0))
         return fail(GPP_ERR_INVALID, "energy and vxc must be finite");
+    if ((s = check_fwd_grid(d, "gpp_sigma_qp"))) return s;
     if ((s = check_inputs(d, in, &din))) return s;
     if ((s = check_array("achtemp", achtemp, d.nw, 16)) ||
         (s = check_array("asxtemp", asxtemp, d.nw, 16)) || (s = check_array("qp", qp, 6, 8)))
@@ -214,7 +236,8 @@ gpp_status gpp_sigma_qp(const gpp_dims *dims, const gpp_inputs *in, double freq_
 size_t gpp_sigma_bwd_workspace(const gpp_dims *dims)
 {
     gpp::Dims32 d;
-    if (check_dims(dims, &d) != GPP_OK) return 0;
+    if (check_dims(dims, &d) != GPP_OK || check_bwd_grid(d, "gpp_sigma_bwd_workspace") != GPP_OK)
+        return 0;
     return gpp::bwd_geometry(d).workspace_bytes;
 }
 
@@ -229,6 +252,7 @@ gpp_status gpp_sigma_bwd(const gpp_dims *dims, const gpp_inputs *in,
     gpp::DevInputs din;
     gpp_status s;
     if ((s = check_dims(dims, &d))) return s;
+    if ((s = check_bwd_grid(d, "gpp_sigma_bwd"))) return s;
     if ((s = check_inputs(d, in, &din))) return s;
     if ((s = check_array("grad_achtemp", grad_achtemp, d.nw, 16)) ||
         (s = check_array("grad_asxtemp", grad_asxtemp, d.nw, 16)))

@@ -115,6 +115,8 @@ gpp_status hip_fail(hipError_t e, const char *where);
 gpp_status check_dims(const gpp_dims *d, Dims32 *out);
 gpp_status check_array(const char *name, const void *p, int64_t elems, size_t align);
 gpp_status check_inputs(const Dims32 &d, const gpp_inputs *in, DevInputs *out);
+gpp_status check_fwd_grid(const Dims32 &d, const char *who);
+gpp_status check_bwd_grid(const Dims32 &d, const char *who);
 bool misaligned(const void *p, size_t a);
 // GPP_OK when the current HIP device is a gfx950, else GPP_ERR_UNSUPPORTED
 // (no device, or another target) with a message naming `who`.  The device's

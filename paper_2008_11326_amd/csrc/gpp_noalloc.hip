@@ -56,6 +56,7 @@ gpp_status gpp_sigma_fwd_noalloc(const gpp_dims *dims, const gpp_inputs *in, dou
     gpp::DevInputs din;
     gpp_status s;
     if ((s = gpp::check_dims(dims, &d))) return s;
+    if ((s = gpp::check_fwd_grid(d, "gpp_sigma_fwd_noalloc"))) return s;
     if ((s = gpp::check_inputs(d, in, &din))) return s;
     if ((s = gpp::check_array("achtemp", achtemp, d.nw, 16)) ||
         (s = gpp::check_array("asxtemp", asxtemp, d.nw, 16)))

@@ -76,11 +76,25 @@ def _call(lib, dims, ins, ach=FAKE + 0x600000, asx=FAKE + 0x600100, ws=None,
     (_dims(ng=1 << 31, npw=1), "ncouls"),
     (_dims(ng=(1 << 26) + 1, npw=1), "ncouls"),
     (_dims(nb=1 << 31), "2^31"),
+    # passes the per-dimension bounds, but 2048 band chunks of 8192 two-column
+    # tiles x 16384 g-tiles would need 2^36 workgroups
+    (_dims(nb=1 << 20, nv=0, ng=1 << 20, npw=1 << 14), "too large for one launch"),
 ])
 def test_invalid_dims(lib, dims, msg):
     assert _call(lib, dims, _inputs()) == 1
     assert msg in lib.gpp_last_error().decode()
     assert lib.gpp_sigma_fwd_workspace(C.byref(dims)) == 0
+
+
+def test_adjoint_grid_beyond_one_launch_is_refused(lib):
+    # the bands kernel's grid: 4 row blocks x 715827883 three-band tiles
+    d = _dims(nb=(1 << 31) - 1, nv=0, ng=1024, npw=16)
+    assert lib.gpp_sigma_bwd_workspace(C.byref(d)) == 0
+    z = C.c_void_p(0)
+    f = C.c_void_p(FAKE + 0x600000)
+    assert lib.gpp_sigma_bwd(C.byref(d), C.byref(_inputs()), f, f, z, z, z, z,
+                             C.c_void_p(FAKE + 0x700000), 1 << 40, None) == 1
+    assert "too large for one launch" in lib.gpp_last_error().decode()
 
 
 @pytest.mark.parametrize("field", [f for f, _ in _lib.GppInputs._fields_])

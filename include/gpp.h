@@ -64,8 +64,10 @@ typedef enum {
 
 /* Loop bounds (Sec. II-A).  Requirements: 0 <= nvband <= number_bands,
  * 0 <= ngpown <= ncouls <= GPP_MAX_NCOULS, 1 <= nfreq <= GPP_MAX_NFREQ,
- * number_bands below 2^31.  number_bands, ncouls or ngpown may be 0
- * (outputs are then 0). */
+ * number_bands below 2^31, and each kernel grid a call launches within
+ * 2^31 workgroups (number_bands x ncouls x ngpown bounds it; a call beyond
+ * returns GPP_ERR_INVALID, its workspace query 0).  number_bands, ncouls or
+ * ngpown may be 0 (outputs are then 0). */
 typedef struct {
     int64_t number_bands;
     int64_t nvband;
@@ -101,8 +103,10 @@ size_t gpp_sigma_fwd_workspace(const gpp_dims *dims);
  *                    16-byte aligned; contents unspecified afterwards
  *   stream:          hipStream_t or NULL
  * Three kernels run on `stream`: the tile kernel writes one partial per
- * workgroup into the workspace, then two fixed-order reduction stages
- * produce the outputs (the separate reduction kernel of Sec. II-A).
+ * workgroup into the workspace (above 512 bands, the band loop of each tile
+ * is split into chunks of at most 512 bands, each with its own partial),
+ * then two fixed-order reduction stages produce the outputs (the separate
+ * reduction kernel of Sec. II-A).
  * Masked (branch B/C) Coulomb-hole terms add nothing to the sums (the
  * branch test is the execution mask of their accumulation), so an output
  * none of whose terms is on branch A comes back exactly 0.

@@ -224,8 +224,81 @@ __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aq
 
 // Occupied bands n0 <= n < n1 (all below nvband) of one lane and one
 // column: Coulomb-hole terms into P1/P2 and screened-exchange terms
-// (ssx / e) into SX, with full complex arithmetic and one reciprocal per
-// term.
+// (ssx / e) into SX.  With d = x - om and s = x + om, the exchange term is
+//   A:  om^2 / (d s) = om^2 conj(d s) r rs,     r = 1/|d|^2, rs = 1/|s|^2
+//   B:  -om / (2 s)  = -om conj(s) rs / 2
+// where d s = x^2 - om^2 has real part fma(Re d, Re s, (Im om)^2) (both
+// factors exact to rounding even where x is near -Re om) and imaginary
+// part -2 Re om Im om, and om conj(s) = (fma(Re om, Re s, (Im om)^2),
+// Im om x).  The band's reciprocals of |d|^2 and of |s|^2 come from two
+// batch inversions (both are at least (Im om)^2, like the hot loop's);
+// the branch picks each term's value by selects, so a value computed for
+// another branch never reaches the sums.
+// Frequencies W0 .. W0+G-1 of one occupied band (see occupied_bands).
+template <int NW, int W0, int G>
+__device__ __forceinline__ void occupied_freqs(int n, int nb, gptr<double> wx, double a, double b,
+                                               double wi2, double wtr, double thr, bool wide,
+                                               cplx om2, cplx qm, cplx (&P1)[NW],
+                                               cplx (&P2)[NW], cplx (&SX)[NW])
+{
+    double xs[G], wd[G], ws[G], r[G], rs[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        xs[k] = wx[(size_t)(W0 + k) * nb + n];
+        const double dr = xs[k] - a, sp = xs[k] + a;
+        wd[k] = fma(dr, dr, wi2);  // |x - om|^2, the branch's wdiffr
+        ws[k] = fma(sp, sp, wi2);  // |x + om|^2
+    }
+    if constexpr (G > 1) {
+        batch_reciprocal<G>(wd, r, wide);
+        batch_reciprocal<G>(ws, rs, wide);
+    } else {
+        r[0] = rcp_nr2(wd[0]);
+        rs[0] = rcp_nr2(ws[0]);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const int w = W0 + k;
+        const double x = xs[k];
+        const double dr = x - a, sp = x + a;
+        const bool isA = wd[k] > thr;
+        const double rc = isA ? r[k] : 0.0;
+        const double rx = rc * x;
+        P1[w].re = fma(rx, qm.re, P1[w].re);
+        P1[w].im = fma(rx, qm.im, P1[w].im);
+        P2[w].re = fma(rc, qm.re, P2[w].re);
+        P2[w].im = fma(rc, qm.im, P2[w].im);
+        // both branches' values carry rs: A = r om^2 conj(d s), B = -om conj(s) / 2
+        const cplx na = cscale(r[k], cmul(om2, cmake(fma(dr, sp, wi2), om2.im)));
+        const cplx nb2 = cmake(-0.5 * fma(a, sp, wi2), -0.5 * (b * x));
+        const bool isB = branch_b_holds(wtr, wd[k]);
+        cplx t;
+        t.re = rs[k] * (isA ? na.re : (isB ? nb2.re : 0.0));
+        t.im = rs[k] * (isA ? na.im : (isB ? nb2.im : 0.0));
+        cmac(SX[w], qm, t);
+    }
+}
+
+// Frequencies per batch-inverted group of an occupied band: all three at
+// up to three frequencies; one at a time beyond, where the groups'
+// reciprocals would raise the kernel's register count above the hot loop's.
+#ifndef GPP_OCC_GROUP
+#define GPP_OCC_GROUP 0
+#endif
+constexpr int occ_group(int nw) { return GPP_OCC_GROUP ? GPP_OCC_GROUP : (nw <= 3 ? nw : 1); }
+
+template <int NW, int W0>
+__device__ __forceinline__ void occupied_groups(int n, int nb, gptr<double> wx, double a, double b,
+                                                double wi2, double wtr, double thr, bool wide,
+                                                cplx om2, cplx qm, cplx (&P1)[NW],
+                                                cplx (&P2)[NW], cplx (&SX)[NW])
+{
+    constexpr int G = NW - W0 < occ_group(NW) ? NW - W0 : occ_group(NW);
+    occupied_freqs<NW, W0, G>(n, nb, wx, a, b, wi2, wtr, thr, wide, om2, qm, P1, P2, SX);
+    if constexpr (W0 + G < NW)
+        occupied_groups<NW, W0 + G>(n, nb, wx, a, b, wi2, wtr, thr, wide, om2, qm, P1, P2, SX);
+}
+
 template <int NW>
 __device__ __forceinline__ void occupied_bands(int n0, int n1, int nb, int ng,
                                                gptr<double2> an_col, gptr<double2> am_col,
@@ -234,33 +307,13 @@ __device__ __forceinline__ void occupied_bands(int n0, int n1, int nb, int ng,
                                                cplx (&SX)[NW])
 {
     const double a = om.re, b = om.im;
+    const cplx om2 = cmake(fma(a, a, -wi2), 2.0 * a * b);  // om^2
+    const bool wide = wi2 >= kMinUnclampedWi2;
     for (int n = n0; n < n1; ++n) {
         const cplx an = cload(an_col + (size_t)n * ng);
         const cplx am = cload(am_col + (size_t)n * ng);
         const cplx qm = cmul_conj(an, am);
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const double x = wx[(size_t)w * nb + n];
-            const double dr = x - a;
-            const double wd = fma(dr, dr, wi2);
-            const bool isA = wd > thr;
-            const double r = isA ? rcp_nr2(wd) : 0.0;
-            const double rx = r * x;
-            P1[w].re = fma(rx, qm.re, P1[w].re);
-            P1[w].im = fma(rx, qm.im, P1[w].im);
-            P2[w].re = fma(r, qm.re, P2[w].re);
-            P2[w].im = fma(r, qm.im, P2[w].im);
-            // ssx / e
-            const cplx d = cmake(dr, -b);    // x - om
-            const cplx s = cmake(x + a, b);  // x + om
-            cplx t = cmake(0.0, 0.0);
-            if (isA) {
-                t = cdiv(cmul(om, om), cmul(d, s));
-            } else if (branch_b_holds(wtr, wd)) {
-                t = cdiv(om, cmake(-2.0 * s.re, -2.0 * s.im));
-            }
-            cmac(SX[w], qm, t);
-        }
+        occupied_groups<NW, 0>(n, nb, wx, a, b, wi2, wtr, thr, wide, om2, qm, P1, P2, SX);
     }
 }
 

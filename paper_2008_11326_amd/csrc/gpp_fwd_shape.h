@@ -36,11 +36,13 @@ constexpr bool fwd_shapes_fit()
 }
 static_assert(fwd_shapes_fit(), "a forward tile's batch inversion holds at most 12 denominators");
 // Minimum waves per SIMD (a VGPR cap) of the forward tile kernels for
-// nfreq = 1..8.  With 7 or 8 frequencies the one-column tile takes 170 and
-// 188 VGPRs, i.e. 2 waves; capped at 168 (3 waves; 2 and 34 bytes of
-// spills) it ran 24 % and 20 % faster.
+// nfreq = 1..8, measured at 512 bands, 32768 rows, 1638 columns (best of 3
+// alternating rounds): nfreq 4 capped at 96 VGPRs (5 waves) 1.5 % faster
+// than at 103 (4); nfreq 7 and 8 capped at 128 (4 waves; 2 and 24 bytes of
+// spills) 9.5 % and 5.1 % faster than at 130 and 144 (3).  nfreq 1 capped
+// for 6 waves and nfreq 6 for 4 ran 0.9 % and 16 % slower.
 #ifndef GPP_FWD_MIN_WAVES
-#define GPP_FWD_MIN_WAVES 1, 1, 1, 1, 1, 1, 3, 3
+#define GPP_FWD_MIN_WAVES 1, 1, 1, 5, 1, 1, 4, 4
 #endif
 constexpr int kFwdMinWaves[8] = {GPP_FWD_MIN_WAVES};
 constexpr int fwd_min_waves(int nw) { return kFwdMinWaves[nw - 1]; }

@@ -142,23 +142,35 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Exchange term of an occupied band: ssx = e sigma, d ssx/d om = e delta.
+// Exchange term of an occupied band: ssx = e sigma, d ssx/d om = e delta,
+// with d = x - om, s = x + om and D = d s = x^2 - om^2:
+//   A:  sigma = om^2 / D,       delta = 2 om x^2 / D^2
+//   B:  sigma = -om / (2 s),    delta = -x / (2 s^2)
+// evaluated without a divide as in the forward: 1/D = conj(D) r rs and
+// 1/s = conj(s) rs with r = 1/|d|^2, rs = 1/|s|^2, where conj(D) =
+// (fma(Re d, Re s, (Im om)^2), 2 Re om Im om) and om conj(s) =
+// (fma(Re om, Re s, (Im om)^2), Im om x).
 __device__ inline void sx_sigma_delta(double x, double a, double b, double wi2, double wtr,
                                       double thr, cplx &sigma, cplx &delta)
 {
-    const cplx om = cmake(a, b);
-    const double dr = x - a;
+    const double dr = x - a, sp = x + a;
     const double wd = fma(dr, dr, wi2);
-    const cplx d = cmake(dr, -b);    // x - om
-    const cplx s = cmake(x + a, b);  // x + om
-    if (wd > thr) {                  // A: sigma = om^2/(d s), delta = 2 om x^2/(d s)^2
-        const cplx ds = cmul(d, s);
-        sigma = cdiv(cmul(om, om), ds);
-        delta = cdiv(cscale(2.0 * x * x, om), cmul(ds, ds));
-    } else if (branch_b_holds(wtr, wd)) {  // B: sigma = -om/(2s), delta = -x/(2 s^2)
-        const cplx s2 = cscale(-2.0, s);
-        sigma = cdiv(om, s2);
-        delta = cdiv(cmake(x, 0.0), cmul(s2, s));
+    if (wd > thr) {  // A
+        const double ws = fma(sp, sp, wi2);
+        const double q = rcp_nr2(wd) * rcp_nr2(ws);
+        const double ab2 = 2.0 * a * b;
+        const cplx cd = cmake(fma(dr, sp, wi2), ab2);  // conj(D)
+        const cplx om2 = cmake(fma(a, a, -wi2), ab2);  // om^2
+        sigma = cscale(q, cmul(om2, cd));
+        const cplx cd2 = cmul(cd, cd);
+        delta = cscale(2.0 * x * x * q * q, cmul(cmake(a, b), cd2));
+    } else if (branch_b_holds(wtr, wd)) {  // B
+        const double ws = fma(sp, sp, wi2);
+        const double h = -0.5 * rcp_nr2(ws);
+        sigma = cmake(fma(a, sp, wi2) * h, (b * x) * h);
+        // conj(s)^2 = (sp^2 - b^2, -2 sp b)
+        const double hh = h * rcp_nr2(ws) * x;
+        delta = cmake(fma(sp, sp, -wi2) * hh, -2.0 * sp * b * hh);
     } else {
         sigma = delta = cmake(0.0, 0.0);
     }

@@ -64,19 +64,27 @@ constexpr int kOctet = 8;                          // lanes that share one row s
 // Minimum waves per SIMD the compiler must allow (register cap): pairs with
 // at most three frequencies (128 VGPRs; more frequencies take 3 waves, as
 // their band sums need more registers), and the bands kernel without and
-// with the daqsmtemp sums.
+// with the daqsmtemp sums.  Bands per bands-kernel workgroup: four, so
+// that the daqsmtemp slab of two columns fills the 8 rows an octet of
+// lanes reduces.  Measured on MI355X at the adjoint workload's sizes
+// against three bands at 5 and 4 waves: the kernel with daqsmtemp 4.5 %
+// faster at nfreq 3 (7.39 against 7.74 ms; at 4 waves, with four bands,
+// it spilled and ran 28 % slower), without daqsmtemp 3 % faster at nfreq 3
+// and 2-2.5x faster at nfreq 4 and 8, where three bands at 5 waves spilled;
+// the whole adjoint 1 % and 5 % faster at nfreq 3 and 4, 1-2 % slower at
+// nfreq 5 and 8.
 #ifndef GPP_BWD_PAIRS_WAVES
 #define GPP_BWD_PAIRS_WAVES 4
 #endif
 constexpr int pairs_waves(int nw) { return nw <= 3 ? GPP_BWD_PAIRS_WAVES : 3; }
 #ifndef GPP_BWD_BANDS_WAVES
-#define GPP_BWD_BANDS_WAVES 5
+#define GPP_BWD_BANDS_WAVES 4
 #endif
 #ifndef GPP_BWD_BANDS_AM_WAVES
-#define GPP_BWD_BANDS_AM_WAVES 4
+#define GPP_BWD_BANDS_AM_WAVES 3
 #endif
 #ifndef GPP_BWD_BAND_TILE
-#define GPP_BWD_BAND_TILE 3
+#define GPP_BWD_BAND_TILE 4
 #endif
 constexpr int kBandTile = GPP_BWD_BAND_TILE;       // bands per bands-kernel workgroup
 // Bands-kernel p-range split (see bwd_geometry): resident bands waves of the
@@ -88,8 +96,14 @@ constexpr int kBandTile = GPP_BWD_BAND_TILE;       // bands per bands-kernel wor
 constexpr long kBandsWaveSlots = 256L * 4 * GPP_BWD_BANDS_WAVES;
 constexpr int kBandsRounds = GPP_BWD_BANDS_ROUNDS;
 constexpr int kMinSegCols = 64;
-static_assert(kBandTile % bwd_group(1) == 0 && kBandTile % bwd_group(8) == 0,
-              "band tile must be whole groups");
+// Bands per batch-inverted group of the bands kernel: the largest divisor
+// of the band tile whose group holds at most 12 denominators.
+constexpr int bands_group(int nw)
+{
+    for (int g = kBandTile; g > 1; --g)
+        if (kBandTile % g == 0 && g * nw <= 12) return g;
+    return 1;
+}
 // daqsmtemp sums of the bands kernel: the slab holds the terms of two G'
 // columns (kBandTile rows each); every kAmCols columns (even) the four
 // waves' row sums are added and written.
@@ -554,7 +568,7 @@ __device__ __forceinline__ void bands_fast(int nb, int ng, int n0, int gc, doubl
                                            const cplx (&an)[kBandTile], AmCtx &amc,
                                            cplx (&acc)[kBandTile])
 {
-    constexpr int G = bwd_group(NW);
+    constexpr int G = bands_group(NW);
     constexpr int Kt = G * NW;
     const int p_lo = amc.p_lo, p_hi = amc.p_hi;
     // om and e of the next column are loaded one iteration ahead, so their
@@ -659,7 +673,7 @@ __device__ __forceinline__ void bands_generic(int nb, int nv, int ng, int n0, in
                                               const cplx (&an)[kBandTile], AmCtx &amc,
                                               cplx (&acc)[kBandTile])
 {
-    constexpr int G = bwd_group(NW);
+    constexpr int G = bands_group(NW);
     for (int p = amc.p_lo; p < amc.p_hi; ++p) {
         const PairState ps = load_pair(wt, ieps, vcoul, p, ng, gc, valid);
         const cplx vce = cmake(ps.ve.re, -ps.ve.im);           // vcoul conj(e)

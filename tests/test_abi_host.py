@@ -208,11 +208,11 @@ def _bwd_segments(lib, nb, nv, ng, npw, nw):
 
 
 def test_bwd_bands_pass_segments(lib):
-    # ~16 rounds of 5120 resident waves, segments of >= 64 G' columns
+    # ~16 rounds of 4096 resident waves, segments of >= 64 G' columns
     assert _bwd_segments(lib, 256, 2, 16384, 819, 3) == 4      # adjoint workload
     assert _bwd_segments(lib, 512, 2, 32768, 1638, 3) == 1     # Si-shaped: grid already long
     assert _bwd_segments(lib, 1024, 4, 65536, 3276, 3) == 1
-    assert _bwd_segments(lib, 9, 2, 200, 130, 3) == 2          # capped by 130 // 64
+    assert _bwd_segments(lib, 8, 2, 200, 130, 3) == 2          # capped by 130 // 64
     assert _bwd_segments(lib, 13, 2, 300, 200, 3) == 3
     assert _bwd_segments(lib, 32, 2, 512, 63, 3) == 1          # fewer than 2 x 64 columns
     assert lib.gpp_sigma_bwd_workspace(C.byref(_dims(256, 2, 16384, 819, 3))) == 483143936

@@ -72,7 +72,7 @@ def test_every_entry_small(gpp, shape, poles):
 
 
 @pytest.mark.parametrize("shape,poles", [
-    ((9, 2, 200, 130, 3), 0.0),    # 2 segments of the G' range, whole band tiles
+    ((8, 2, 200, 130, 3), 0.0),    # 2 segments of the G' range, whole band tiles
     ((13, 2, 300, 200, 3), 0.1),   # 3 segments (66/67/67 columns), ragged last band tile
 ])
 def test_every_entry_segmented_bands_pass(gpp, shape, poles):

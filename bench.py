@@ -13,8 +13,8 @@ frequency, seed 2; inputs resident in HBM.  Prints one JSON line on stdout.
 `value` is the fp64 FLOP rate the hardware counts (the paper's measure,
 Eq. 2): the fp64 VALU instructions of the tile kernel, counted once with
 rocprofv3 for the same sources and workload (profiles/gpp_fwd_tiles_*.json,
-keyed by a digest of the forward sources), divided by the time measured
-here.  Beside it: the algorithmic rate (21 fp64 operations per Coulomb-hole
+keyed by a digest of the forward sources' code, comments left out), divided
+by the time measured here.  Beside it: the algorithmic rate (21 fp64 operations per Coulomb-hole
 and per screened-exchange term, fixed by the method), the FMA-share
 ceiling of Sec. III (the closing FMA-ratio paragraph), the share of the
 fp64 FMA rate a microbenchmark reaches on this GPU, and the Si-shaped
@@ -27,6 +27,7 @@ import ctypes as C
 import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -45,11 +46,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _code_only(text):
+    """Source text without comments and with runs of whitespace collapsed, so
+    that editing a comment does not change the digest (the sources hold no
+    string literal with a comment marker in it)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def fwd_source_digest():
     h = hashlib.sha256()
     for f in FWD_SOURCES:
-        with open(os.path.join(ROOT, "paper_2008_11326_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2008_11326_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -77,13 +77,6 @@ __device__ __forceinline__ void cmac(cplx &acc, cplx a, cplx b) {
     acc.re = fma(a.re, b.re, fma(-a.im, b.im, acc.re));
     acc.im = fma(a.re, b.im, fma(a.im, b.re, acc.im));
 }
-// a / b with an IEEE-rounded real division of the scaled numerator.
-__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
-    double den = fma(b.re, b.re, b.im * b.im);
-    double inv = 1.0 / den;
-    cplx num = cmul_conj(a, b);
-    return {num.re * inv, num.im * inv};
-}
 
 // 1/d for normal d: the hardware estimate refined by two Newton-Raphson
 // steps r <- r + r (1 - d r).  Each step squares the relative error; two

@@ -23,7 +23,9 @@
 // product's range), and the branch-A test is the execution mask around
 // each term's four fused multiply-adds, so a masked term adds nothing and
 // costs no select.  Occupied bands (n < nvband) also evaluate the
-// screened-exchange term with full complex arithmetic.
+// screened-exchange term, from batch-inverted |x - om|^2 and |x + om|^2
+// instead of a complex divide (gpp_fwd_tile.h).  Above 512 bands each
+// tile's band loop is split into chunks, each a tile of its own.
 //
 // Each workgroup (4 waves) writes one partial per output into the
 // workspace; two reduction kernels then sum the partials in a fixed order

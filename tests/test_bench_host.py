@@ -37,7 +37,10 @@ def test_counter_records_follow_the_source_digest(tmp_path, monkeypatch):
     got = bench.kernel_counters("w")
     assert got is not None and got["path"] == os.path.join("profiles", "gpp_fwd_tiles_w.json")
     assert bench.kernel_counters("other") is None
-    (csrc / bench.FWD_SOURCES[0]).write_text("// changed\n")
+    # a comment edit keeps the record, a code edit drops it
+    (csrc / bench.FWD_SOURCES[0]).write_text(f"// {bench.FWD_SOURCES[0]}, reworded\n/* and */\n")
+    assert bench.kernel_counters("w") is not None
+    (csrc / bench.FWD_SOURCES[0]).write_text("int x;\n")
     assert bench.kernel_counters("w") is None
 
 

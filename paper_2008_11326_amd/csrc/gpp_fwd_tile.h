@@ -222,18 +222,6 @@ __device__ __forceinline__ void ch_group(int n, int nb, int ng, gptr<double2> aq
     ch_group_an<NW, BU>(n, nb, ng, an, am_col, wx, a, wi2, thr, wide, P1, P2);
 }
 
-// Occupied bands n0 <= n < n1 (all below nvband) of one lane and one
-// column: Coulomb-hole terms into P1/P2 and screened-exchange terms
-// (ssx / e) into SX.  With d = x - om and s = x + om, the exchange term is
-//   A:  om^2 / (d s) = om^2 conj(d s) r rs,     r = 1/|d|^2, rs = 1/|s|^2
-//   B:  -om / (2 s)  = -om conj(s) rs / 2
-// where d s = x^2 - om^2 has real part fma(Re d, Re s, (Im om)^2) (both
-// factors exact to rounding even where x is near -Re om) and imaginary
-// part -2 Re om Im om, and om conj(s) = (fma(Re om, Re s, (Im om)^2),
-// Im om x).  The band's reciprocals of |d|^2 and of |s|^2 come from two
-// batch inversions (both are at least (Im om)^2, like the hot loop's);
-// the branch picks each term's value by selects, so a value computed for
-// another branch never reaches the sums.
 // Frequencies W0 .. W0+G-1 of one occupied band (see occupied_bands).
 template <int NW, int W0, int G>
 __device__ __forceinline__ void occupied_freqs(int n, int nb, gptr<double> wx, double a, double b,
@@ -299,6 +287,19 @@ __device__ __forceinline__ void occupied_groups(int n, int nb, gptr<double> wx, 
         occupied_groups<NW, W0 + G>(n, nb, wx, a, b, wi2, wtr, thr, wide, om2, qm, P1, P2, SX);
 }
 
+// Occupied bands n0 <= n < n1 (all below nvband) of one lane and one
+// column: Coulomb-hole terms into P1/P2 and screened-exchange terms
+// (ssx / e) into SX.  With d = x - om and s = x + om, the exchange term is
+//   A:  om^2 / (d s) = om^2 conj(d s) r rs,     r = 1/|d|^2, rs = 1/|s|^2
+//   B:  -om / (2 s)  = -om conj(s) rs / 2
+// where d s = x^2 - om^2 has real part fma(Re d, Re s, (Im om)^2) (both
+// factors exact to rounding even where x is near -Re om) and imaginary
+// part -2 Re om Im om, and om conj(s) = (fma(Re om, Re s, (Im om)^2),
+// Im om x).  The band's reciprocals of |d|^2 and of |s|^2 come from two
+// batch inversions per group of frequencies (both are at least
+// (Im om)^2, like the hot loop's denominators); the branch picks each
+// term's value by selects, so a value computed for another branch never
+// reaches the sums.
 template <int NW>
 __device__ __forceinline__ void occupied_bands(int n0, int n1, int nb, int ng,
                                                gptr<double2> an_col, gptr<double2> am_col,

@@ -133,6 +133,42 @@ def test_every_tile_variant_vs_oracle(gpp, uneven_by_nfreq, nw, sched, bu, monke
     plan.close()
 
 
+@pytest.fixture(scope="module")
+def many():
+    """3000 tiny uneven states (1-6 bands, 1-100 rows, 0-5 G' columns, some
+    empty), their oracle outputs and device copies."""
+    rng = np.random.default_rng(31)
+    dims = []
+    for _ in range(3000):
+        nb = int(rng.integers(1, 7))
+        ng = int(rng.integers(1, 101))
+        dims.append(I.Dims(nb, int(rng.integers(0, nb + 1)), ng,
+                           int(rng.integers(0, min(ng, 5) + 1)), 3))
+    probs = [I.make_problem(d, [31, k], 0.05 if k % 3 == 0 else 0.0) for k, d in enumerate(dims)]
+    refs = [oracle.sigma_fwd(p, nthreads=1) for p in probs]
+    return probs, refs, [to_device(p) for p in probs]
+
+
+@pytest.mark.parametrize("sched", [0, 3, 4])
+def test_many_small_states(gpp, many, sched, monkeypatch):
+    """One plan over 3000 tiny states (the state lookup of the flat grid,
+    the per-XCD queues' regions and the per-state reductions over many
+    states), each schedule alone, against the oracle."""
+    import torch
+    monkeypatch.setenv("GPP_BATCHED_SCHEDULE", str(sched))
+    probs, refs, dev = many
+    say(f"[batched] {len(probs)} small states, schedule {sched}")
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    ach, asx = gpp.sigma_batched(plan, dev)
+    torch.cuda.synchronize()
+    assert plan.info()["schedule"] == sched
+    a, x = ach.cpu().numpy(), asx.cpu().numpy()
+    for k, ref in enumerate(refs):
+        assert_parity(a[k], ref[0], ref[2], f"state {k} achtemp")
+        assert_parity(x[k], ref[1], ref[3], f"state {k} asxtemp")
+    plan.close()
+
+
 def test_tiny_imaginary_lanes(gpp, tmp_path, monkeypatch):
     """States whose tiles mix lanes with (Im om)^2 below 2^-60 (one-by-one
     reciprocals, exact poles) with ordinary lanes, against the oracle."""

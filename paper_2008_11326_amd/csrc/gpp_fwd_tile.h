@@ -17,11 +17,15 @@ namespace gpp {
 // Column tiles per block of the tile walk: 0 walks each g-tile through all
 // column tiles in turn; Q > 0 walks blocks of Q column tiles through all
 // g-tiles, so that the block's aqsmtemp columns (Q * cols * 16 bytes per
-// band: 1 MB at 64 two-column tiles and 512 bands) stay in an XCD's L2
-// while the g-tiles' aqsntemp rows stream past.  At 64 the L2 misses of
-// the Si-shaped forward fall from 16.8 to 6.1 GB per launch.
+// band: 2 MB at 128 two-column tiles and 512 bands, half an XCD's L2) stay
+// in the L2 while the g-tiles' aqsntemp rows stream past, each row fetched
+// once per block.  Measured with band chunks of 512 on MI355X: Q = 128
+// took the HBM-side traffic of the 1024-band forward from 45.3 GB (Q = 64)
+// to 39.1 GB and its time, the 512-band one's and the 64-state batched
+// workload's down by 0.4-0.9 %; Q = 160 and 192 (2.5 and 3 MB) thrashed
+// the L2 (85 and 98 GB) and ran slower.
 #ifndef GPP_FWD_COL_BLOCK
-#define GPP_FWD_COL_BLOCK 64
+#define GPP_FWD_COL_BLOCK 128
 #endif
 
 // (g-tile, column tile, band chunk) of a tile index, a bijection on

@@ -221,7 +221,9 @@ typedef struct gpp_plan gpp_plan;
  */
 gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan **out);
 
-/* Device workspace bytes gpp_sigma_batched needs with this plan. */
+/* Device workspace bytes gpp_sigma_batched needs with this plan: 256 bytes
+ * of queue counters plus one 32*nfreq-byte partial row per tile at most
+ * (gpp_plan_info.total_tiles), rounded up to 256 bytes; 0 for NULL. */
 size_t gpp_plan_workspace(const gpp_plan *plan);
 
 typedef struct {

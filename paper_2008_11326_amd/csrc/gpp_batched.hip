@@ -13,11 +13,13 @@
 // tile of the mean (or, in the XCD-chunked schedule, each XCD takes one
 // contiguous, equally costly chunk of the list and its waves round-robin
 // inside it).  Each wave keeps running sums for the state it is in and
-// writes exactly one partial row per state (zeros for states it never
-// touches) into slot [state][wave]; a second kernel adds each state's W rows
-// in a fixed order.  Waves never wait on each other, so the grid needs no
-// co-residency and every wave reaches its exit.  The per-tile arithmetic is
-// the plain forward's (gpp_fwd_tile.h).
+// writes one partial row for each state it touches, at a slot fixed by
+// where its first tile of the state lies (static_slot); a second kernel adds
+// each state's rows in a fixed order.  The rows of a state are thus at most
+// min(W, its tiles) per XCD range it meets, so the workspace grows with the
+// tile count, not with states x waves.  Waves never wait on each other, so
+// the grid needs no co-residency and every wave reaches its exit.  The
+// per-tile arithmetic is the plain forward's (gpp_fwd_tile.h).
 #include "gpp_device.h"
 #include "gpp_fwd_tile.h"
 #include "gpp_internal.h"
@@ -31,15 +33,57 @@ constexpr int kBatWaves = 4;
 constexpr long kFlatRun = GPP_BAT_FLAT_RUN;  // flat form: consecutive workgroups per XCD
 constexpr int kBatThreads = kBatWaves * kWave;
 
-// Write the wave's running sums for state s (wave-uniform values) and
-// clear them.
+// Partial-row slot of a static-schedule wave for schedule position s, whose
+// tiles are [b, e) = [st[s].tile_begin, st[s+1].tile_begin).  The waves that
+// walk a range of tiles with stride W (all waves over the whole list, or one
+// XCD's waves over its chunk [xc[x], xc[x+1])) meet min(W, L) of the state's
+// L tiles in that range first, each at a different offset below min(W, L)
+// from the range's first tile of the state; that offset numbers the wave's
+// row.  The state's rows start at st[s].chunk_begin and take the ranges of
+// lower XCDs first, so they fill [chunk_begin[s], chunk_begin[s+1]) exactly
+// (the plan computes the same counts).  xc == nullptr: one range.
+__device__ __forceinline__ long static_slot(const StateDesc *__restrict__ st, int s, long first,
+                                            const long *__restrict__ xc, int xcd, uint32_t per,
+                                            uint32_t rem)
+{
+    const long b = st[s].tile_begin, e = st[s + 1].tile_begin;
+    long slot = st[s].chunk_begin, f = b;
+    if (xc) {
+        for (int x = 0; x < xcd; ++x) {
+            const long lo = xc[x] > b ? xc[x] : b, hi = xc[x + 1] < e ? xc[x + 1] : e;
+            const long wx = (long)(per + ((uint32_t)x < rem ? 1 : 0)) * 4;
+            if (hi > lo) slot += hi - lo < wx ? hi - lo : wx;
+        }
+        if (xc[xcd] > f) f = xc[xcd];
+    }
+    return slot + (first - f);
+}
+
+// The schedule position k in [lo, nstates) of the state holding item v of
+// the list (a tile, or a queue chunk when CHUNK), given that state lo starts
+// at or before v: the last k with start(k) <= v, so empty states are never
+// returned.  st[nstates] is the sentinel holding the total, which v is below.
+template <bool CHUNK>
+__device__ __forceinline__ int find_state(const StateDesc *__restrict__ st, int lo, int nstates,
+                                          long v)
+{
+    int hi = nstates;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((CHUNK ? st[mid].chunk_begin : st[mid].tile_begin) <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Write the wave's running sums (wave-uniform values) into partial row
+// `slot` and clear them.
 template <int NW>
-__device__ __forceinline__ void flush_state(const StateDesc *__restrict__ st, int s, int wave,
-                                            int nwaves, int lane, cplx (&ach)[NW],
-                                            cplx (&asx)[NW], double *__restrict__ partials)
+__device__ __forceinline__ void flush_state(long slot, int lane, cplx (&ach)[NW], cplx (&asx)[NW],
+                                            double *__restrict__ partials)
 {
     if (lane == 0) {
-        double *dst = partials + ((size_t)st[s].out_index * nwaves + wave) * (4 * NW);
+        double *dst = partials + (size_t)slot * (4 * NW);
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             dst[4 * w + 0] = ach[w].re;
@@ -92,9 +136,10 @@ batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_til
     // this wave's XCD over that XCD's contiguous chunk of the tile list, so
     // one XCD's L2 serves each g-tile as in the plain forward.
     long t0 = wave, step = nwaves, t_end = total_tiles;
+    const uint32_t kXcd = kXcdCount, per = gridDim.x / kXcd, rem = gridDim.x % kXcd;
+    const int xcd = (int)(blockIdx.x % kXcd);
     if (xcd_chunks) {
-        const uint32_t kXcd = 8, x = blockIdx.x % kXcd, i = blockIdx.x / kXcd;
-        const uint32_t per = gridDim.x / kXcd, rem = gridDim.x % kXcd;
+        const uint32_t x = (uint32_t)xcd, i = blockIdx.x / kXcd;
         const long waves_x = (long)(per + (x < rem ? 1 : 0)) * kBatWaves;
         t0 = xcd_chunks[x] + (long)i * kBatWaves + wid;
         step = waves_x;
@@ -108,12 +153,18 @@ batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_til
 #pragma unroll
     for (int w = 0; w < NW; ++w) ach[w] = asx[w] = cmake(0.0, 0.0);
 
-    int s = 0;  // schedule position of the state holding tile t
+    int s = 0;        // schedule position of the state holding tile t
+    long first = -1;  // the wave's first tile of state s (-1: none yet)
     for (long t = t0; t < t_end; t += step) {
-        while (t >= st[s + 1].tile_begin) {  // st[nstates].tile_begin == total_tiles
-            flush_state<NW>(st, s, wave, nwaves, lane, ach, asx, partials);
-            ++s;
+        if (t >= st[s + 1].tile_begin) {  // st[nstates].tile_begin == total_tiles
+            if (first >= 0)
+                flush_state<NW>(static_slot(st, s, first, xcd_chunks, xcd, per, rem), lane, ach,
+                                asx, partials);
+            first = -1;
+            // the states in between hold none of this wave's tiles
+            s = find_state<false>(st, s + 1, nstates, t);
         }
+        if (first < 0) first = t;
         const StateDesc d = st[s];
         cplx a[NW], x[NW];
         state_tile<NW, BU>(d, t - d.tile_begin, lane, a, x);
@@ -125,7 +176,9 @@ batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_til
             asx[w].im = to_uniform(asx[w].im + x[w].im);
         }
     }
-    for (; s < nstates; ++s) flush_state<NW>(st, s, wave, nwaves, lane, ach, asx, partials);
+    if (first >= 0)
+        flush_state<NW>(static_slot(st, s, first, xcd_chunks, xcd, per, rem), lane, ach, asx,
+                        partials);
 }
 
 // Work-queue form: waves take chunks of chunk_tiles consecutive tiles (never
@@ -143,7 +196,7 @@ batched_persistent(const StateDesc *__restrict__ st, int nstates, long total_til
 template <int NW, int BU>
 __global__ void __launch_bounds__(kBatThreads)
 __attribute__((amdgpu_waves_per_eu(bat_cols(NW) == 2 ? GPP_BAT_WAVES2 : (NW <= 3 ? 4 : 1))))
-batched_queue(const StateDesc *__restrict__ st, long nchunks, int chunk_tiles,
+batched_queue(const StateDesc *__restrict__ st, int nstates, long nchunks, int chunk_tiles,
               unsigned long long *__restrict__ counter, const long *__restrict__ queue_begin,
               double *__restrict__ partials)
 {
@@ -166,8 +219,8 @@ batched_queue(const StateDesc *__restrict__ st, long nchunks, int chunk_tiles,
             if (++qi >= nq) break;
             continue;
         }
-        if (c < st[s].chunk_begin) s = 0;  // moved back to an earlier region
-        while (c >= st[s + 1].chunk_begin) ++s;
+        if (c < st[s].chunk_begin || c >= st[s + 1].chunk_begin)
+            s = find_state<true>(st, c < st[s].chunk_begin ? 0 : s + 1, nstates, c);
         const StateDesc d = st[s];
         const long t0 = d.tile_begin + (c - d.chunk_begin) * chunk_tiles;
         const long tmax = st[s + 1].tile_begin;
@@ -285,8 +338,9 @@ __global__ void zero_counters(unsigned long long *counter, int n)
     if ((int)threadIdx.x < n) counter[threadIdx.x] = 0ull;
 }
 
-// Per state (one workgroup per schedule position k): the sum of its chunk
-// rows [chunk_begin[k], chunk_begin[k+1]) in a fixed order.
+// Per state (one workgroup per schedule position k): the sum of its partial
+// rows [chunk_begin[k], chunk_begin[k+1]) (queue chunks, flat workgroups or
+// static-schedule slots) in a fixed order.
 template <int NW>
 __global__ void __launch_bounds__(256)
 batched_reduce_chunks(const StateDesc *__restrict__ st, const double *__restrict__ partials,
@@ -304,41 +358,6 @@ batched_reduce_chunks(const StateDesc *__restrict__ st, const double *__restrict
     for (long c = c0 + threadIdx.x; c < c1; c += 256) {
 #pragma unroll
         for (int j = 0; j < R; ++j) acc[j] += partials[(size_t)c * R + j];
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const double v = wave_sum(acc[j]);
-        if (lane == 0) red[wid][j] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < R) {
-        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                         red[3][threadIdx.x];
-        const int w = threadIdx.x / 4, c = threadIdx.x % 4;
-        double *dst = reinterpret_cast<double *>(c < 2 ? ach + (size_t)s * NW + w
-                                                       : asx + (size_t)s * NW + w);
-        dst[c & 1] = v;
-    }
-}
-
-// achtemp[s][w], asxtemp[s][w] = sum over the W partial rows of state s, in
-// a fixed order (thread t adds rows t, t+256, ..., then a fixed tree).
-template <int NW>
-__global__ void __launch_bounds__(256)
-batched_reduce(const double *__restrict__ partials, int nwaves, double2 *__restrict__ ach,
-               double2 *__restrict__ asx)
-{
-    constexpr int R = 4 * NW;
-    __shared__ double red[4][R];
-    const int s = blockIdx.x;
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    double acc[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) acc[j] = 0.0;
-    const double *base = partials + (size_t)s * nwaves * R;
-    for (int i = threadIdx.x; i < nwaves; i += 256) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) acc[j] += base[(size_t)i * R + j];
     }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -392,12 +411,8 @@ const void *batched_kernel(int nw, int bu, int sched)
 template <int NW>
 static void launch_reduce(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st)
 {
-    if (L.sched == kSchedQueue || L.sched == kSchedXcdQueues || L.sched == kSchedFlat)
-        hipLaunchKernelGGL(batched_reduce_chunks<NW>, dim3(L.nstates), dim3(256), 0, st, L.desc,
-                           L.partials, ach, asx);
-    else
-        hipLaunchKernelGGL(batched_reduce<NW>, dim3(L.nstates), dim3(256), 0, st, L.partials,
-                           L.blocks * kBatWaves, ach, asx);
+    hipLaunchKernelGGL(batched_reduce_chunks<NW>, dim3(L.nstates), dim3(256), 0, st, L.desc,
+                       L.partials, ach, asx);
 }
 
 hipError_t launch_batched(const BatchedLaunch &L, double2 *ach, double2 *asx, hipStream_t st)
@@ -418,8 +433,9 @@ hipError_t launch_batched(const BatchedLaunch &L, double2 *ach, double2 *asx, hi
         hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, st, L.counter, kXcdCount);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const long *qb = L.sched == kSchedXcdQueues ? L.queue_begin : nullptr;
-        void *args[] = {(void *)&L.desc,    (void *)&L.nchunks, (void *)&L.chunk_tiles,
-                        (void *)&L.counter, (void *)&qb,        (void *)&L.partials};
+        void *args[] = {(void *)&L.desc,    (void *)&L.nstates, (void *)&L.nchunks,
+                        (void *)&L.chunk_tiles, (void *)&L.counter, (void *)&qb,
+                        (void *)&L.partials};
         e = hipLaunchKernel(k, dim3(L.blocks), dim3(kBatThreads), args, 0, st);
     } else {
         const int nwaves = L.blocks * kBatWaves;

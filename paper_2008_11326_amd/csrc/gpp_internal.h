@@ -63,7 +63,8 @@ struct StateDesc {
     const double *vcoul, *wx;
     int nb, nv, ng, np;
     long tile_begin;   // first global tile of this state
-    long chunk_begin;  // first work-queue chunk of this state
+    long chunk_begin;  // first partial row of this state: work-queue chunk, flat-form
+                       // workgroup or static-schedule slot, by schedule
     int out_index;     // position in the caller's state order
     int pad;
 };

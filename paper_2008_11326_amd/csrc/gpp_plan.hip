@@ -319,6 +319,37 @@ void queue_regions(const gpp_plan *pl, const std::vector<int> &perm, long *out)
     out[X] = total_chunks;
 }
 
+// Partial rows per state (schedule order) of a static schedule: the waves
+// that walk a range of the tile list with stride W meet min(W, L) of a
+// state's L tiles in that range first, and each of them writes one row
+// (the kernel numbers them the same way, static_slot in gpp_batched.hip).
+// Round-robin: one range, the whole list, W = all waves; XCD chunks: one
+// range per XCD, W = that XCD's waves.  The total is at most the tile count.
+std::vector<long> static_slots(const gpp_plan *pl, const std::vector<int> &perm, int blocks,
+                               int sched)
+{
+    const int X = gpp::kXcdCount;
+    std::vector<long> out(perm.size(), 0);
+    long xc[gpp::kXcdCount + 1];
+    if (sched == gpp::kSchedXcdChunks) xcd_chunks(pl, perm, blocks, xc);
+    const long per = blocks / X, rem = blocks % X;
+    long b = 0;
+    for (size_t k = 0; k < perm.size(); ++k) {
+        const long n = pl->tiles[perm[k]], e = b + n;
+        if (sched == gpp::kSchedXcdChunks) {
+            for (int x = 0; x < X; ++x) {
+                const long lo = std::max(b, xc[x]), hi = std::min(e, xc[x + 1]);
+                const long wx = (per + (x < rem ? 1 : 0)) * 4;
+                if (hi > lo) out[k] += std::min(wx, hi - lo);
+            }
+        } else {
+            out[k] = std::min((long)blocks * 4, n);
+        }
+        b = e;
+    }
+    return out;
+}
+
 gpp_status upload(gpp_plan *pl, int cand, const gpp_inputs *in, hipStream_t st)
 {
     const int order = pl->cands[cand].order;
@@ -330,6 +361,10 @@ gpp_status upload(gpp_plan *pl, int cand, const gpp_inputs *in, hipStream_t st)
     hipError_t e = hipEventSynchronize(pl->staged);  // the previous copy has read the staging
     if (e != hipSuccess) return hip_fail(e, "gpp_sigma_batched: staging event");
     const std::vector<int> perm = schedule(pl, order);
+    const int sched = pl->cands[cand].sched;
+    const bool is_static = sched == gpp::kSchedRoundRobin || sched == gpp::kSchedXcdChunks;
+    const std::vector<long> slots =
+        is_static ? static_slots(pl, perm, pl->cands[cand].blocks, sched) : std::vector<long>();
     long tb = 0, cb = 0;
     for (int k = 0; k < pl->nstates; ++k) {
         const int s = perm[k];
@@ -350,10 +385,11 @@ gpp_status upload(gpp_plan *pl, int cand, const gpp_inputs *in, hipStream_t st)
         o.out_index = s;
         o.pad = 0;
         tb += pl->tiles[s];
-        // work-queue chunks, or for the flat form the state's workgroups
-        cb += pl->cands[cand].sched == gpp::kSchedFlat
-                  ? flat_workgroups(d)
-                  : (pl->tiles[s] + kQueueChunkTiles - 1) / kQueueChunkTiles;
+        // partial rows: the state's workgroups (flat form), work-queue
+        // chunks, or static-schedule slots
+        cb += sched == gpp::kSchedFlat ? flat_workgroups(d)
+              : is_static             ? slots[k]
+                                      : (pl->tiles[s] + kQueueChunkTiles - 1) / kQueueChunkTiles;
     }
     memset(&pl->h_desc[pl->nstates], 0, sizeof(gpp::StateDesc));
     pl->h_desc[pl->nstates].tile_begin = tb;
@@ -601,7 +637,12 @@ gpp_status gpp_plan_create(int32_t nstates, const gpp_dims *dims_host, gpp_plan 
             pl->cands.push_back(c);
             pl->max_waves = std::max(pl->max_waves, c.blocks * 4);
             const bool queue = cmb[0] == gpp::kSchedQueue || cmb[0] == gpp::kSchedXcdQueues;
-            rows = std::max(rows, queue ? (size_t)nchunks : (size_t)nstates * c.blocks * 4);
+            size_t need = (size_t)nchunks;
+            if (!queue) {
+                need = 0;
+                for (long v : static_slots(pl, schedule(pl, cmb[1]), c.blocks, cmb[0])) need += v;
+            }
+            rows = std::max(rows, need);
         }
     if (pl->cands.empty()) {
         delete pl;

@@ -8,7 +8,7 @@ ncouls=65536, ngpown=3276, nfreq=3, 1 % of wtilde planted within 1e-6 of a
 frequency, seed 2; inputs resident in HBM.  Prints one JSON line on stdout.
 
     python bench.py [--steps K] [--warmup W] [--workload large|si|small|adjoint]
-    python bench.py --leg adjoint|batched|batched_small|si   # one leg alone, for profiling
+    python bench.py --leg adjoint|batched|batched_small|batched_tiny|si   # one leg alone
 
 `value` is the fp64 FLOP rate the hardware counts (the paper's measure,
 Eq. 2): the fp64 VALU instructions of the tile kernel, counted once with
@@ -20,7 +20,9 @@ ceiling of Sec. III (the closing FMA-ratio paragraph), the share of the
 fp64 FMA rate a microbenchmark reaches on this GPU, and the Si-shaped
 workload's rate.  The roofline block compares the algorithmic rate of the
 tile kernel with the MI355X fp64 vector-ALU peak.  The CPU baseline times
-the plain oracle on a bounded slice of the same workload.
+the plain oracle on a bounded slice of the same workload.  The extra legs
+time the adjoint against the forward, and the batched plan against
+separate forwards on 64 uneven states, 256 small ones and 3000 tiny ones.
 """
 import argparse
 import ctypes as C
@@ -341,17 +343,19 @@ def batched_leg(gpp, I, stream, reps=3):
                     "generator, seed 1000+s for state s (not the seed-3 host values)"}
 
 
-def batched_small_leg(gpp, I, stream, reps=5):
-    """Many small states (256 states of 32..128 bands and 1024..4096 rows):
-    one graph-replayed gpp_sigma_batched call against 256 gpp_sigma_fwd
+def batched_small_leg(gpp, I, stream, reps=5, tiny=False):
+    """Many small states (256 states of 32..128 bands and 1024..4096 rows;
+    with tiny, 3000 states of 1..6 bands, 1..100 rows and 1..5 G' columns):
+    one graph-replayed gpp_sigma_batched call against as many gpp_sigma_fwd
     calls in a row, both straight through the C ABI with argument structs
     built once, so that neither side pays the Python binding's per-call
     checks.  Each small state alone leaves most of the GPU idle."""
     import torch
     from paper_2008_11326_amd import _lib
     lib = _lib.load()
-    dims = I.small_batched_dims()
-    states = [I.make_problem_device(dd, 2000 + k) for k, dd in enumerate(dims)]
+    dims = I.tiny_batched_dims() if tiny else I.small_batched_dims()
+    seed0 = 3000 if tiny else 2000
+    states = [I.make_problem_device(dd, seed0 + k) for k, dd in enumerate(dims)]
     nw = dims[0].nfreq
     dev = torch.device("cuda:0")
     keys = ("aqsmtemp", "aqsntemp", "I_eps_array", "wtilde_array", "vcoul", "wx_array")
@@ -400,9 +404,12 @@ def batched_small_leg(gpp, I, stream, reps=5):
             "plan": {k: info[k] for k in ("bands_per_group", "schedule_order", "schedule",
                                            "waves", "candidates", "from_cache")},
             "timing": "best of 5, HIP events on the launch stream; both sides call the C ABI",
-            "data": "synthetic: 256 state sizes from default_rng(5) (32..128 bands, "
-                    "1024..4096 rows, ngpown = ncouls // 20, nvband 2, nfreq 3), values "
-                    "drawn on the device, seed 2000+s for state s"}
+            "data": ("synthetic: 3000 state sizes from default_rng(31) (1..6 bands, 1..100 rows, "
+                     "1..5 G' columns, nvband min(2, bands), nfreq 3), values drawn on the "
+                     "device, seed 3000+s for state s") if tiny else
+                    ("synthetic: 256 state sizes from default_rng(5) (32..128 bands, "
+                     "1024..4096 rows, ngpown = ncouls // 20, nvband 2, nfreq 3), values "
+                     "drawn on the device, seed 2000+s for state s")}
 
 
 def si_leg(gpp, I, stream, steps=5, warmup=2):
@@ -429,7 +436,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Si-shaped, adjoint, batched and FMA-peak legs")
-    ap.add_argument("--leg", choices=("all", "adjoint", "batched", "batched_small", "si"),
+    ap.add_argument("--leg", choices=("all", "adjoint", "batched", "batched_small",
+                                      "batched_tiny", "si"),
                     default="all",
                     help="adjoint, batched or si: run only that leg and print its JSON "
                          "(for per-kernel profiling); all: the benchmark line")
@@ -452,7 +460,8 @@ def main():
     stream = torch.cuda.current_stream(torch.device("cuda:0"))
     if args.leg != "all":
         leg = {"adjoint": adjoint_leg, "batched": batched_leg,
-               "batched_small": batched_small_leg, "si": si_leg}[args.leg]
+               "batched_small": batched_small_leg, "si": si_leg,
+               "batched_tiny": lambda *a: batched_small_leg(*a, tiny=True)}[args.leg]
         log(f"[bench] {args.leg} leg only")
         print(json.dumps({"leg": args.leg, **leg(gpp, I, stream)}), flush=True)
         return
@@ -513,6 +522,8 @@ def main():
         out["batched"] = batched_leg(gpp, I, stream)
         log("[bench] batched leg, many small states")
         out["batched_small"] = batched_small_leg(gpp, I, stream)
+        log("[bench] batched leg, many tiny states")
+        out["batched_tiny"] = batched_small_leg(gpp, I, stream, tiny=True)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded slice")

@@ -212,6 +212,22 @@ def small_batched_dims(nfreq: int = 3) -> List[Dims]:
                         SMALL_BATCHED_BANDS, SMALL_BATCHED_ROWS256)
 
 
+TINY_BATCHED_SEED = 31
+TINY_BATCHED_STATES = 3000
+
+
+def tiny_batched_dims(nfreq: int = 3) -> List[Dims]:
+    """Sizes of a set of many tiny states (1-6 bands, 1-100 G rows, 1-5 G'
+    columns, nvband min(2, bands)), drawn from default_rng(31)."""
+    rng = np.random.default_rng(TINY_BATCHED_SEED)
+    out = []
+    for _ in range(TINY_BATCHED_STATES):
+        nb = int(rng.integers(1, 7))
+        ng = int(rng.integers(1, 101))
+        out.append(Dims(nb, min(2, nb), ng, int(rng.integers(1, min(ng, 5) + 1)), nfreq))
+    return out
+
+
 def make_batched(seed: int = BATCHED_SEED, nstates: int = BATCHED_STATES,
                  nfreq: int = 3, states: Optional[Sequence[int]] = None):
     """Yield (index, Problem) per state; state s draws from default_rng([seed, s])."""

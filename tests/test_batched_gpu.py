@@ -174,6 +174,49 @@ def test_many_small_states(gpp, many, sched, monkeypatch):
     plan.close()
 
 
+MAX_STATES_BASE = [I.Dims(1, 1, 1, 1, 3), I.Dims(3, 2, 64, 2, 3), I.Dims(2, 0, 65, 3, 3),
+                   I.Dims(5, 5, 100, 4, 3), I.Dims(4, 1, 30, 0, 3), I.Dims(6, 2, 129, 5, 3),
+                   I.Dims(1, 0, 17, 1, 3), I.Dims(2, 2, 200, 2, 3)]
+
+
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 4])
+def test_the_largest_state_count(gpp, sched, monkeypatch):
+    """GPP_MAX_STATES = 65536 states in one plan, through the C ABI: state s
+    has the sizes and inputs of MAX_STATES_BASE[s % 8] (one of them empty),
+    so the oracle values of eight problems check every state; each schedule
+    alone, and its workspace within one partial row per tile."""
+    import ctypes as C
+    import torch
+    from paper_2008_11326_amd import _lib
+    lib = _lib.load()
+    monkeypatch.setenv("GPP_BATCHED_SCHEDULE", str(sched))
+    nbase, nmax = len(MAX_STATES_BASE), 65536
+    probs = [I.make_problem(d, [43, k], 0.05 if k % 2 else 0.0)
+             for k, d in enumerate(MAX_STATES_BASE)]
+    refs = [oracle.sigma_fwd(p, nthreads=1) for p in probs]
+    dev = [to_device(p) for p in probs]
+    keys = ("aqsmtemp", "aqsntemp", "I_eps_array", "wtilde_array", "vcoul", "wx_array")
+    one = [_lib.GppInputs(*[C.c_void_p(t[k].data_ptr()) for k in keys]) for t in dev]
+    ins = (_lib.GppInputs * nmax)(*[one[s % nbase] for s in range(nmax)])
+    say(f"[batched] {nmax} states, schedule {sched}")
+    plan = gpp.Plan([probs[s % nbase].dims.as_tuple() for s in range(nmax)])
+    info = plan.info()
+    row = 4 * 3 * 8
+    assert plan.workspace_bytes <= 256 + (info["total_tiles"] * row + 255) // 256 * 256
+    ach = torch.empty((nmax, 3), dtype=torch.complex128, device="cuda:0")
+    asx = torch.empty_like(ach)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda:0")
+    _lib.check(lib.gpp_sigma_batched(plan._h, ins, ach.data_ptr(), asx.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), None), "gpp_sigma_batched")
+    torch.cuda.synchronize()
+    assert plan.info()["schedule"] == sched
+    a, x = ach.cpu().numpy(), asx.cpu().numpy()
+    for k, ref in enumerate(refs):
+        assert_parity(a[k::nbase], ref[0], ref[2], f"base problem {k} achtemp")
+        assert_parity(x[k::nbase], ref[1], ref[3], f"base problem {k} asxtemp")
+    plan.close()
+
+
 def test_tiny_imaginary_lanes(gpp, tmp_path, monkeypatch):
     """States whose tiles mix lanes with (Im om)^2 below 2^-60 (one-by-one
     reciprocals, exact poles) with ordinary lanes, against the oracle."""

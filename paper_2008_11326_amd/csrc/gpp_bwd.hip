@@ -794,22 +794,33 @@ bwd_bands(int nb, int nv, int ng, int np, long nwg, int nbt, int ngb, int nps,
 }
 
 // daqsmtemp[n][p] = sum over row blocks of the partials (p < np), 0 for
-// columns np..ncouls-1.  One thread per output element, fixed order.
+// columns np..ncouls-1.  One thread per output element, fixed order.  The
+// nb * np sums come first in the grid and the zero columns after them, so
+// that the workgroups which read run together instead of one in twenty
+// across the whole grid.
 __global__ void reduce_am(int nb, int ng, int np, int ngb, const double2 *__restrict__ part,
                           double2 *__restrict__ grad_am)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)nb * ng) return;
-    const int n = (int)(i / ng), col = (int)(i - (long)n * ng);
-    double re = 0.0, im = 0.0;
-    if (col < np) {
+    const long nsum = (long)nb * np;
+    if (i < nsum) {
+        const int n = (int)(i / np), col = (int)(i - (long)n * np);
+        double re = 0.0, im = 0.0;
+        // unrolled so that eight loads are in flight; the additions keep
+        // their order
+#pragma unroll 8
         for (int b = 0; b < ngb; ++b) {
             const double2 v = part[((size_t)b * nb + n) * np + col];
             re += v.x;
             im += v.y;
         }
+        grad_am[(size_t)n * ng + col] = make_double2(re, im);
+        return;
     }
-    grad_am[i] = make_double2(re, im);
+    const long j = i - nsum, nz = ng - np;
+    if (nz <= 0 || j >= (long)nb * nz) return;
+    const int n = (int)(j / nz);
+    grad_am[(size_t)n * ng + np + (j - (long)n * nz)] = make_double2(0.0, 0.0);
 }
 
 // daqsntemp = sum of the nps segment partials, in segment order.
@@ -819,6 +830,7 @@ __global__ void reduce_an(long nbg, int nps, const double2 *__restrict__ part,
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nbg) return;
     double re = 0.0, im = 0.0;
+#pragma unroll 4
     for (int s = 0; s < nps; ++s) {
         const double2 v = part[(size_t)s * nbg + i];
         re += v.x;

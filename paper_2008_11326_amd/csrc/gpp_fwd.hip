@@ -44,7 +44,8 @@ constexpr int kFwdThreads = kFwdWaves * kWave;
 // fwd_cols and fwd_bands, and a cap on VGPRs through a minimum number of
 // waves per SIMD from fwd_min_waves (gpp_internal.h), all chosen by
 // measurement on MI355X.  At nfreq 3, two columns per wave let each
-// aqsntemp load serve both: 153 VGPRs (3 waves per SIMD) with 2-band
+// aqsntemp load serve both: 153 VGPRs when measured, 156 with the
+// divide-free exchange term (3 waves per SIMD either way) with 2-band
 // groups, 2.8-3.1 % faster than one column with 3-band groups (105 VGPRs,
 // 4 waves); three columns need about 200 VGPRs (2 waves) and measured
 // 3-30 % slower.

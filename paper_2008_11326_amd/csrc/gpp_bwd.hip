@@ -505,11 +505,16 @@ __device__ __forceinline__ void am_put(AmCtx &a, int p, int u, cplx an, cplx vz)
 }
 
 // After column p: when the slab is full (two columns) or p is the range's
-// last column, add each slab row over the wave (lane (tj, tk) adds 8
-// entries of row tj, rotated so the 8 lanes of an octet hit distinct banks,
-// then the octet adds its 8 sums) into red; every kAmCols columns, and at
-// the end, add red over the four waves and write the partials.  Every wave
-// of the workgroup calls this for the same columns.
+// last column, add each slab row over the wave (lane (tj, tk) adds the
+// entries tk, tk + 8, ..., tk + 56 of row tj, then the octet adds its 8
+// sums) into red.  An octet thus reads 128 contiguous bytes at a time, and
+// the rows start at staggered offsets ((i + tj) mod 8), so that the two
+// octets the LDS serves per clock fall in different halves of its banks:
+// measured on gfx950, such a 16-byte read takes 4 LDS cycles with no bank
+// conflict, against 8 cycles (4 of them conflict stalls) when each lane
+// reads 8 consecutive entries.  Every kAmCols columns, and at the end, add
+// red over the four waves and write the partials.  Every wave of the
+// workgroup calls this for the same columns.
 __device__ __forceinline__ void am_column_done(AmCtx &a, int p)
 {
     const int c = (p - a.p_lo) & 1;
@@ -523,7 +528,7 @@ __device__ __forceinline__ void am_column_done(AmCtx &a, int p)
         if (tj < rows) {
 #pragma unroll
             for (int i = 0; i < kOctet; ++i) {
-                const double2 v = a.st->slab[a.wid][tj][kOctet * tk + ((i + tk + tj) & (kOctet - 1))];
+                const double2 v = a.st->slab[a.wid][tj][tk + kOctet * ((i + tj) & (kOctet - 1))];
                 sr += v.x;
                 si += v.y;
             }

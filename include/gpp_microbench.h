@@ -43,6 +43,25 @@ int gpp_mb_copy(const void *src, void *dst, int64_t bytes, int blocks, void *str
 int gpp_mb_read(const void *buf, int64_t window_bytes, int shared, int blocks, int reps,
                 double *out, void *stream);
 
+/* LDS access patterns of 16-byte elements, for the bank-conflict and
+ * LDS-cycle counters (SQ_LDS_BANK_CONFLICT, SQ_LDS_IDX_ACTIVE): `blocks`
+ * workgroups of 64 lanes, each on its own LDS array of 8 rows x 64
+ * elements (e = (64 r + j, 1.0) at row r, entry j), `reps` rounds.  Lane l
+ * is (tj, tk) = (l / 8, l % 8).  Per round:
+ *   pattern 0: 8 writes, lane l writes entry l of every row;
+ *   pattern 1: 8 reads of row tj, entries 8 tk + ((c + tk + tj) mod 8),
+ *              c = 0..7 (each lane 8 consecutive entries, rotated);
+ *   pattern 2: 8 reads of row tj, entries tk + 8 ((c + tj) mod 8) (each
+ *              octet of lanes 128 contiguous bytes, rows staggered);
+ *   pattern 3: 8 reads of row tj, entries 8 tk + c (not rotated).
+ * Pattern 0 writes (64 (8 i + r) + l, 1.0) in round i; afterwards lane l
+ * reads entry 63 - l of row l % 8.  out: device double [blocks * 64], lane
+ * l's value: for the reads the sum over all rounds of re + im of what it
+ * read, for the writes the real part read back,
+ * 64 (8 (reps - 1) + l % 8) + 63 - l.  Returns as the functions above
+ * (1 also for a pattern outside 0..3). */
+int gpp_mb_lds(int pattern, int blocks, int reps, double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,7 @@ _SIGNATURES = [
      [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
     ("gpp_mb_read", C.c_int,
      [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    ("gpp_mb_lds", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
 ]
 EXPORTED = [s[0] for s in _SIGNATURES]
 

@@ -510,11 +510,12 @@ __device__ __forceinline__ void am_put(AmCtx &a, int p, int u, cplx an, cplx vz)
 // sums) into red.  An octet thus reads 128 contiguous bytes at a time, and
 // the rows start at staggered offsets ((i + tj) mod 8), so that the two
 // octets the LDS serves per clock fall in different halves of its banks:
-// measured on gfx950, such a 16-byte read takes 4 LDS cycles with no bank
-// conflict, against 8 cycles (4 of them conflict stalls) when each lane
-// reads 8 consecutive entries.  Every kAmCols columns, and at the end, add
-// red over the four waves and write the partials.  Every wave of the
-// workgroup calls this for the same columns.
+// measured on gfx950 (gpp_mb_lds patterns 2 and 1), such a 16-byte read
+// takes 4 LDS cycles with no bank conflict, against 8 cycles (4 of them
+// conflict stalls) when each lane reads 8 consecutive entries.  Every
+// kAmCols columns, and at the end, add red over the four waves and write
+// the partials.  Every wave of the workgroup calls this for the same
+// columns.
 __device__ __forceinline__ void am_column_done(AmCtx &a, int p)
 {
     const int c = (p - a.p_lo) & 1;

@@ -1,7 +1,8 @@
 // gpp_microbench.hip -- empirical machine ceilings for the roofline: an
 // fp64 FMA issue-rate kernel, a streaming copy of known size (the
-// reference for scaling hardware byte counters) and a read-bandwidth
-// kernel whose window size selects the cache level it measures.  Declared in
+// reference for scaling hardware byte counters), a read-bandwidth kernel
+// whose window size selects the cache level it measures, and LDS access
+// patterns for the bank-conflict counters.  Declared in
 // include/gpp_microbench.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -72,6 +73,41 @@ __global__ void __launch_bounds__(256) mb_read(const double2 *__restrict__ buf, 
     out[(size_t)blockIdx.x * 256 + threadIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
+// LDS access patterns (gpp_mb_lds).  The memory clobber after each round
+// keeps the compiler from reusing the previous round's loads or dropping
+// overwritten stores, so every round issues its 8 LDS instructions.
+__global__ void __launch_bounds__(64) mb_lds(int pattern, int reps, double *out)
+{
+    __shared__ double2 s[8][64];
+    const int l = threadIdx.x, tj = l >> 3, tk = l & 7;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s[r][l] = make_double2(64.0 * r + l, 1.0);
+    __syncthreads();
+    double acc = 0.0;
+    if (pattern == 0) {
+        for (int i = 0; i < reps; ++i) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) s[r][l] = make_double2(64.0 * (8 * i + r) + l, 1.0);
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        }
+        __syncthreads();
+        acc = s[l & 7][63 - l].x;
+    } else {
+        for (int i = 0; i < reps; ++i) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int e = pattern == 1 ? 8 * tk + ((c + tk + tj) & 7)
+                              : pattern == 2 ? tk + 8 * ((c + tj) & 7)
+                                             : 8 * tk + c;
+                const double2 v = s[tj][e];
+                acc += v.x + v.y;
+            }
+            asm volatile("" ::: "memory");
+        }
+    }
+    out[(size_t)blockIdx.x * 64 + l] = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -105,6 +141,16 @@ int gpp_mb_read(const void *buf, int64_t window_bytes, int shared, int blocks, i
     if (gpp::check_device("gpp_mb_read") != GPP_OK) return 5;
     hipLaunchKernelGGL(mb_read, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
                        (const double2 *)buf, (long)(window_bytes / 16), shared ? 1 : 0, reps,
+                       out);
+    return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
+int gpp_mb_lds(int pattern, int blocks, int reps, double *out, void *stream)
+{
+    if (pattern < 0 || pattern > 3 || blocks <= 0 || reps <= 0 || !out) return 1;
+    if ((uintptr_t)out % 8) return 1;
+    if (gpp::check_device("gpp_mb_lds") != GPP_OK) return 5;
+    hipLaunchKernelGGL(mb_lds, dim3(blocks), dim3(64), 0, (hipStream_t)stream, pattern, reps,
                        out);
     return hipGetLastError() == hipSuccess ? 0 : 2;
 }

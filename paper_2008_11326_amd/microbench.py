@@ -3,9 +3,13 @@ bandwidth and the read bandwidth of vL1D, L2, MALL and HBM
 (include/gpp_microbench.h).  Prints one JSON line.
 
     python -m paper_2008_11326_amd.microbench [--copy-mib 2048]
+    python -m paper_2008_11326_amd.microbench --lds-only
 
 The copy moves exactly 2 * bytes (read + write); under rocprofv3 --pmc its
 FETCH_SIZE / WRITE_SIZE give the factor between counted and real bytes.
+With --lds-only it launches the four LDS access patterns once each, in
+pattern order (one dispatch of gpp::mb_lds per pattern), for the
+bank-conflict counters.
 """
 import argparse
 import ctypes as C
@@ -19,6 +23,8 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--no-read-levels", dest="read_levels", action="store_false",
                     help="skip the per-level read-bandwidth kernels")
+    ap.add_argument("--lds-only", action="store_true",
+                    help="only the LDS access patterns, one launch each")
     args = ap.parse_args()
 
     import torch
@@ -46,6 +52,17 @@ def main():
         return best
 
     res = {"device": props.name, "compute_units": cus}
+    if args.lds_only:
+        blocks, reps = 64, 4096
+        out = torch.empty(blocks * 64, dtype=torch.float64, device=dev)
+        for pattern in range(4):
+            _lib.check(lib.gpp_mb_lds(pattern, blocks, reps, C.c_void_p(out.data_ptr()),
+                                      C.c_void_p(st.cuda_stream)), "gpp_mb_lds")
+        torch.cuda.synchronize()
+        res["lds_patterns"] = {"blocks": blocks, "reps": reps,
+                               "lds_instructions_per_pattern": blocks * reps * 8}
+        print(json.dumps(res), flush=True)
+        return
     fma = {}
     for waves_per_simd in (2, 4, 8):
         blocks = cus * waves_per_simd  # 4 waves per workgroup

@@ -308,6 +308,10 @@ def test_no_device_is_unsupported(lib):
     assert lib.gpp_mb_copy(C.c_void_p(FAKE), C.c_void_p(FAKE + 0x100000), 4096, 1, None) == 5
     assert lib.gpp_mb_read(C.c_void_p(FAKE), 4096, 0, 1, 1, C.c_void_p(FAKE + 0x100000),
                            None) == 5
+    assert lib.gpp_mb_lds(2, 1, 1, C.c_void_p(FAKE), None) == 5
+    for bad in ((4, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 0)):
+        assert lib.gpp_mb_lds(*bad, C.c_void_p(FAKE), None) == 1
+    assert lib.gpp_mb_lds(0, 1, 1, None, None) == 1
 
 
 def _qp(lib, dims, ins=None, step=0.5, energy=0.1, vxc=0.0, qp=FAKE + 0xC00000,

@@ -1,8 +1,9 @@
 """The calibration kernels behind the measured ceilings and the counter
 scaling (include/gpp_microbench.h): the streaming copy must move every byte
 it claims (FETCH_SIZE / WRITE_SIZE are scaled by what they read for it),
-the read kernel must read the window it is given, and the FMA kernel must
-run the chains it counts.  Each is checked against values computed on the
+the read kernel must read the window it is given, the FMA kernel must
+run the chains it counts, and the LDS pattern kernel must touch the entries
+it states.  Each is checked against values computed on the
 host."""
 import ctypes as C
 
@@ -94,3 +95,34 @@ def test_fma_chains_closed_form(lib):
     got = out.cpu().numpy().reshape(blocks, 256)
     for b in range(blocks):
         assert np.allclose(got[b], want, rtol=1e-13, atol=0.0)
+
+
+def _lds_reference(pattern, blocks, reps):
+    """mb_lds's per-lane result, computed on the host (include/gpp_microbench.h)."""
+    lane = np.arange(64)
+    tj, tk = lane // 8, lane % 8
+    c = np.arange(8)
+    if pattern == 0:
+        one = 64 * (8 * (reps - 1) + lane % 8) + 63 - lane
+    else:
+        if pattern == 1:
+            e = 8 * tk[:, None] + (c[None, :] + tk[:, None] + tj[:, None]) % 8
+        elif pattern == 2:
+            e = tk[:, None] + 8 * ((c[None, :] + tj[:, None]) % 8)
+        else:
+            e = 8 * tk[:, None] + c[None, :]
+        one = reps * ((64 * tj[:, None] + e) + 1).sum(axis=1)
+    return np.tile(one.astype(np.float64), blocks)
+
+
+@pytest.mark.parametrize("pattern", [0, 1, 2, 3])
+def test_lds_patterns_read_and_write_what_they_claim(lib, pattern):
+    """The LDS pattern kernel behind the bank-conflict measurements touches
+    exactly the entries its header states (sums of small integers, exact)."""
+    import torch
+    blocks, reps = 3, 9
+    out = torch.empty(blocks * 64, dtype=torch.float64, device="cuda:0")
+    say(f"[mb] lds pattern {pattern}")
+    assert lib.gpp_mb_lds(pattern, blocks, reps, C.c_void_p(out.data_ptr()), None) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), _lds_reference(pattern, blocks, reps))

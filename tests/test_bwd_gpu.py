@@ -56,6 +56,9 @@ def all_entries(rows, cols):
     ((6, 2, 100, 5, 3), 0.0), ((5, 2, 64, 3, 3), 0.2), ((7, 7, 130, 4, 3), 0.1),
     ((4, 0, 65, 3, 3), 0.0), ((8, 3, 257, 2, 2), 0.0), ((1, 1, 1, 1, 1), 0.0),
     ((10, 2, 70, 3, 5), 0.0), ((13, 2, 300, 2, 8), 0.1),
+    # every other frequency count: 4 (the last with the pairs kernel's band
+    # sums, 2-band groups), 6 (2-band groups) and 7 (1-band groups)
+    ((9, 2, 150, 3, 4), 0.1), ((7, 3, 90, 3, 6), 0.0), ((6, 2, 80, 2, 7), 0.1),
 ])
 def test_every_entry_small(gpp, shape, poles):
     prob = I.make_problem(I.Dims(*shape), sum(shape) + 3, poles)

@@ -86,7 +86,7 @@ def _plan_bands(nw):
 
 # every batched tile variant: frequency count x persistent schedule x bands
 # per group, and the flat grid (the plain forward's tile) per frequency count
-VARIANTS = [(nw, sched, bu) for nw in (1, 2, 3, 4, 5, 8) for sched in (0, 1, 2, 3)
+VARIANTS = [(nw, sched, bu) for nw in range(1, 9) for sched in (0, 1, 2, 3)
             for bu in _plan_bands(nw)] + [(nw, 4, None) for nw in (1, 2, 4, 5, 6, 7, 8)]
 
 

@@ -112,9 +112,13 @@ def test_every_entry_tiny_imaginary_lanes(gpp, frac):
     check_entries("wtilde_array", g["wtilde_array"], prob, ga, gs, all_entries(npw, ng))
 
 
-def test_skipped_outputs_and_determinism(gpp):
-    prob = I.make_problem(I.Dims(9, 2, 200, 6, 3), 5)
-    ga, gs = I.make_upstream_grad(3, np.random.default_rng(1))
+@pytest.mark.parametrize("nw", range(1, 9))
+def test_skipped_outputs_and_determinism(gpp, nw):
+    """Without the aqsmtemp and I_eps gradients the bands kernel runs its
+    form without the aqsmtemp sums (a kernel of its own per frequency
+    count): its aqsntemp gradient equals the full call's bit for bit."""
+    prob = I.make_problem(I.Dims(9, 2, 200, 6, nw), 5)
+    ga, gs = I.make_upstream_grad(nw, np.random.default_rng(1))
     full = gpu_grads(gpp, prob, ga, gs)
     again = gpu_grads(gpp, prob, ga, gs)
     part = gpu_grads(gpp, prob, ga, gs, want=(False, True, False, True))

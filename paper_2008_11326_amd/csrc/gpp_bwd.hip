@@ -118,10 +118,11 @@ __global__ void bwd_prepare(int nb, int nw, const double *__restrict__ wx,
                             const double2 *__restrict__ ga, double2 *__restrict__ gh,
                             double2 *__restrict__ xgh)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // 64-bit: nfreq x number_bands passes 2^31 from 2^28 bands on
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nw) gh[i] = make_double2(0.5 * ga[i].x, 0.5 * ga[i].y);
-    if (i < nw * nb) {
-        const int w = i / nb;
+    if (i < (long)nw * nb) {
+        const int w = (int)(i / nb);
         const double x = wx[i];
         xgh[i] = make_double2(0.5 * x * ga[w].x, 0.5 * x * ga[w].y);
     }
@@ -895,9 +896,9 @@ static hipError_t launch_bwd_nw(const Dims32 &d, const BwdGeometry &geo, const D
     double2 *am_part = reinterpret_cast<double2 *>(ws + up(geo.gh_elems) + up(geo.xgh_elems));
     double2 *an_part = reinterpret_cast<double2 *>(ws + up(geo.gh_elems) + up(geo.xgh_elems) +
                                                    up(geo.am_part_elems));
-    const int prep = d.nw * d.nb > d.nw ? d.nw * d.nb : d.nw;
-    hipLaunchKernelGGL(bwd_prepare, dim3((prep + 255) / 256), dim3(256), 0, st, d.nb, d.nw,
-                       in.wx, ga, gh, xgh);
+    const long prep = (long)d.nw * d.nb > d.nw ? (long)d.nw * d.nb : d.nw;
+    hipLaunchKernelGGL(bwd_prepare, dim3((unsigned)((prep + 255) / 256)), dim3(256), 0, st,
+                       d.nb, d.nw, in.wx, ga, gh, xgh);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (out.grad_wt || out.grad_ieps) {

@@ -64,7 +64,7 @@ typedef enum {
 
 /* Loop bounds (Sec. II-A).  Requirements: 0 <= nvband <= number_bands,
  * 0 <= ngpown <= ncouls <= GPP_MAX_NCOULS, 1 <= nfreq <= GPP_MAX_NFREQ,
- * number_bands below 2^31, and each kernel grid a call launches within
+ * number_bands <= GPP_MAX_NBANDS, and each kernel grid a call launches within
  * 2^31 workgroups (number_bands x ncouls x ngpown bounds it; a call beyond
  * returns GPP_ERR_INVALID, its workspace query 0).  number_bands, ncouls or
  * ngpown may be 0 (outputs are then 0). */
@@ -78,6 +78,7 @@ typedef struct {
 
 #define GPP_MAX_NFREQ 8
 #define GPP_MAX_NCOULS (1 << 26)
+#define GPP_MAX_NBANDS (1 << 30)
 
 /* Device input arrays (read only).  A pointer may be NULL only when its
  * array has no elements. */

@@ -45,8 +45,11 @@ gpp_status check_dims(const gpp_dims *d, gpp::Dims32 *out)
     if (d->ngpown > d->ncouls)
         return fail(GPP_ERR_INVALID, "ngpown=%lld > ncouls=%lld", (long long)d->ngpown,
                     (long long)d->ncouls);
-    if (d->number_bands > kMax32 || d->ngpown > kMax32)
-        return fail(GPP_ERR_INVALID, "dimension >= 2^31");
+    // band indices plus a tile's few bands stay far inside 32 bits
+    if (d->number_bands > GPP_MAX_NBANDS)
+        return fail(GPP_ERR_INVALID, "number_bands=%lld > %d", (long long)d->number_bands,
+                    GPP_MAX_NBANDS);
+    if (d->ngpown > kMax32) return fail(GPP_ERR_INVALID, "dimension >= 2^31");
     // rows are addressed with 32-bit byte offsets inside the kernels
     if (d->ncouls > GPP_MAX_NCOULS)
         return fail(GPP_ERR_INVALID, "ncouls=%lld > %d", (long long)d->ncouls, GPP_MAX_NCOULS);

@@ -75,7 +75,8 @@ def _call(lib, dims, ins, ach=FAKE + 0x600000, asx=FAKE + 0x600100, ws=None,
     (_dims(nb=-1), "negative"),
     (_dims(ng=1 << 31, npw=1), "ncouls"),
     (_dims(ng=(1 << 26) + 1, npw=1), "ncouls"),
-    (_dims(nb=1 << 31), "2^31"),
+    (_dims(nb=1 << 31), "number_bands"),
+    (_dims(nb=(1 << 30) + 1, nv=0, ng=64, npw=1), "number_bands"),
     # passes the per-dimension bounds, but 2048 band chunks of 8192 two-column
     # tiles x 16384 g-tiles would need 2^36 workgroups
     (_dims(nb=1 << 20, nv=0, ng=1 << 20, npw=1 << 14), "too large for one launch"),
@@ -86,9 +87,18 @@ def test_invalid_dims(lib, dims, msg):
     assert lib.gpp_sigma_fwd_workspace(C.byref(dims)) == 0
 
 
+def test_largest_band_count_is_accepted(lib):
+    # GPP_MAX_NBANDS = 2^30 bands: 2^21 chunks of 512 bands for one tile
+    d = _dims(nb=1 << 30, nv=0, ng=64, npw=1)
+    assert lib.gpp_sigma_fwd_workspace(C.byref(d)) > 0
+    assert lib.gpp_sigma_bwd_workspace(C.byref(d)) > 0
+
+
 def test_adjoint_grid_beyond_one_launch_is_refused(lib):
-    # the bands kernel's grid: 4 row blocks x 715827883 three-band tiles
-    d = _dims(nb=(1 << 31) - 1, nv=0, ng=1024, npw=16)
+    # the bands kernel's grid: 8 row blocks x 2^28 four-band tiles = 2^31
+    # workgroups; the forward's 2^27 fit
+    d = _dims(nb=1 << 30, nv=0, ng=2048, npw=16)
+    assert lib.gpp_sigma_fwd_workspace(C.byref(d)) > 0
     assert lib.gpp_sigma_bwd_workspace(C.byref(d)) == 0
     z = C.c_void_p(0)
     f = C.c_void_p(FAKE + 0x600000)

@@ -94,6 +94,33 @@ def test_largest_band_count_is_accepted(lib):
     assert lib.gpp_sigma_bwd_workspace(C.byref(d)) > 0
 
 
+def test_last_error_is_per_thread(lib):
+    """gpp_last_error is thread-local: two threads that fail differently at
+    the same time each read their own message, and the calling thread's
+    message is untouched."""
+    import threading
+    assert _call(lib, _dims(nw=9), _inputs()) == 1
+    mine = lib.gpp_last_error().decode()
+    assert "nfreq" in mine
+    gate = threading.Barrier(2)
+    seen = {}
+
+    def worker(key, dims):
+        st = _call(lib, dims, _inputs())
+        gate.wait()  # both threads have failed before either reads
+        seen[key] = (st, lib.gpp_last_error().decode())
+
+    ts = [threading.Thread(target=worker, args=("nv", _dims(nv=9))),
+          threading.Thread(target=worker, args=("np", _dims(npw=101)))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert seen["nv"][0] == 1 and "nvband" in seen["nv"][1] and "ngpown" not in seen["nv"][1]
+    assert seen["np"][0] == 1 and "ngpown" in seen["np"][1] and "nvband" not in seen["np"][1]
+    assert lib.gpp_last_error().decode() == mine
+
+
 def test_adjoint_grid_beyond_one_launch_is_refused(lib):
     # the bands kernel's grid: 8 row blocks x 2^28 four-band tiles = 2^31
     # workgroups; the forward's 2^27 fit

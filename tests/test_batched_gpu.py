@@ -280,6 +280,36 @@ def test_new_input_pointers_and_outputs(gpp, uneven, tmp_path, monkeypatch):
     plan.close()
 
 
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_capturing_stream_is_refused(gpp, uneven, tmp_path, monkeypatch):
+    """A stream that is being captured is refused before anything is
+    enqueued (the plan replays a graph of its own); the plan then works as
+    usual on an ordinary stream."""
+    import torch
+    monkeypatch.setenv("GPP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    probs, refs, dev = uneven
+    plan = gpp.Plan([p.dims.as_tuple() for p in probs])
+    nw = probs[0].dims.nfreq
+    out = (torch.empty((len(probs), nw), dtype=torch.complex128, device="cuda:0"),
+           torch.empty((len(probs), nw), dtype=torch.complex128, device="cuda:0"))
+    ws = torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device="cuda:0")
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=side):
+        with pytest.raises(gpp.GppError) as err:
+            gpp.sigma_batched(plan, dev, out=out, workspace=ws, stream=side.cuda_stream)
+    assert "capturing" in str(err.value)
+    assert plan.info()["tuned"] == 0  # nothing ran, not even the tuner
+    torch.cuda.synchronize()
+    ach, asx = gpp.sigma_batched(plan, dev, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    for k, ref in enumerate(refs):
+        assert_parity(ach[k].cpu().numpy(), ref[0], ref[2], f"state {k} achtemp")
+        assert_parity(asx[k].cpu().numpy(), ref[1], ref[3], f"state {k} asxtemp")
+    plan.close()
+
+
 TUNE_SCRIPT = r"""
 import json, sys, os
 sys.path.insert(0, {root!r})

@@ -499,6 +499,11 @@ def main():
                                f"(one gpp_sigma_fwd), algorithmic FLOPs",
                      "launch_ms": round(r["launch_ms"], 4)},
         "max_rel_err_vs_oracle": max_rel_err(args.workload, res),
+        # the paper's best figure (Table I, v8): another machine, workload and
+        # FLOP count (counted on the V100), so context only, not a target
+        "paper_context": {"tflops": 3.71, "pct_of_fp64_peak": 55,
+                          "machine": "NVIDIA V100, 6.7 TFLOP/s fp64 peak",
+                          "workload": "BerkeleyGW Si-214, 2 frequencies (Table I, v8)"},
     }
     if counted:
         out["fp64_counted"] = {
